@@ -1,0 +1,221 @@
+"""Benchmark of the HC searching phase on one MI355X.
+
+Default workload (single pattern per launch): three 256 MiB iid texts over
+sigma = 4, 20, 64 symbols; for each, 100 patterns of each length
+m in {2, 4, ..., 1024} copied from the text at seeded offsets; one step
+searches all 3000 (pattern, text) pairs, one launch each, with the texts
+resident in HBM. value = text bytes scanned per second over the timed steps.
+
+Prints one JSON line (rank 0). Extra objects:
+  roofline      the search kernel's algorithmic bytes per launch over its
+                average launch time (HIP events around each launch on the
+                launch stream), against the 8 TB/s HBM peak;
+  cpu_baseline  the oracle (C brute force, all host cores) on a bounded
+                sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single",
+                    choices=["single", "markov", "planted"])
+    ap.add_argument("--per-length", type=int, default=100, help="patterns per (sigma, m)")
+    ap.add_argument("--sigmas", default="4,20,64")
+    ap.add_argument("--lengths", default=None, help="comma list of m (default: the workload's)")
+    ap.add_argument("--text-mib", type=int, default=256)
+    ap.add_argument("--segment", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--params", default=None, help="q,alpha,w for every pattern")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-patterns", type=int, default=1,
+                    help="oracle sample: patterns per (sigma, m)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--detail", action="store_true", help="print per-(sigma, m) figures to stderr")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2310_15711_amd import binding as B
+    from paper_2310_15711_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    B.lib()
+    n = args.text_mib << 20
+
+    # ---------------------------------------------------------------- inputs
+    t0 = time.time()
+    texts = {}
+    if args.workload == "single":
+        sigmas = [int(s) for s in args.sigmas.split(",")]
+        lengths = [int(v) for v in args.lengths.split(",")] if args.lengths else list(W.SINGLE_LENGTHS)
+        for s in sigmas:
+            texts[s] = W.single_text(s, n)
+        pats = [(s, m, off, x) for s in sigmas for m in lengths
+                for off, x in W.single_patterns(texts[s], s, m, args.per_length)]
+        workload = (f"single-pattern HC: {len(sigmas)} iid texts x {args.text_mib} MiB "
+                    f"(sigma {args.sigmas}), m in {lengths}, {args.per_length} patterns each")
+    elif args.workload == "markov":
+        lengths = [int(v) for v in args.lengths.split(",")] if args.lengths else list(W.MARKOV_LENGTHS)
+        texts[27] = W.markov_text(n)
+        pats = [(27, m, off, x) for m in lengths
+                for off, x in W.markov_patterns(texts[27], m, args.per_length)]
+        workload = (f"single-pattern HC on order-2 Markov text ({args.text_mib} MiB, 27 symbols), "
+                    f"m in {lengths}, {args.per_length} patterns each")
+    else:
+        p = W.planted_config()
+        texts[4] = p.y
+        pats = [(4, 32, p.source, p.x)]
+        workload = "planted: 1 MiB iid ACGT, m=32, 100 planted copies"
+    log(f"inputs ready in {time.time() - t0:.1f}s: {len(pats)} patterns")
+
+    dtexts = {s: torch.from_numpy(y).to(dev) for s, y in texts.items()}
+    params = tuple(int(v) for v in args.params.split(",")) if args.params else None
+    handles = [B.hc_preprocess(x, params) for (_, _, _, x) in pats]
+    launch = (args.segment, args.schedule, args.variant, 0)
+    cap = 1 << 25
+    out = torch.empty(cap, dtype=torch.int64, device=dev)
+    counts = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    ev0 = [[torch.cuda.Event(enable_timing=True) for _ in pats] for _ in range(args.steps)]
+    ev1 = [[torch.cuda.Event(enable_timing=True) for _ in pats] for _ in range(args.steps)]
+
+    def step(k):
+        for i, (s, m, off, x) in enumerate(pats):
+            if k is not None:
+                ev0[k][i].record(stream)
+            B.hc_search_async(handles[i], dtexts[s], out, counts[i:i + 1], launch=launch,
+                              stream=stream)
+            if k is not None:
+                ev1[k][i].record(stream)
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    t_wall = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    per_launch = np.array([[ev0[k][i].elapsed_time(ev1[k][i]) for i in range(len(pats))]
+                           for k in range(args.steps)])
+    ms_total = start.elapsed_time(stop)
+    ms_step = ms_total / args.steps
+
+    cnt = counts.cpu().numpy()
+    text_bytes = sum(int(texts[s].size) for (s, _, _, _) in pats)
+    value = text_bytes / (ms_step * 1e-3) / 1e9
+    launch_ms = per_launch.mean(axis=0)                      # per pattern, mean over steps
+    avg_launch_ms = float(launch_ms.mean())
+    # algorithmic bytes per launch: the text once, the positions written,
+    # F and x read
+    infos = [B.hc_pattern_info(h) for h in handles]
+    alg_bytes = np.array([texts[s].size + 8 * int(c) + inf["F"].size * inf["w"] // 8 + m
+                          for (s, m, _, _), c, inf in zip(pats, cnt, infos)], dtype=np.float64)
+    if (cnt < 0).any():
+        raise RuntimeError("a launch reported an incomplete ordered output")
+    achieved = float(alg_bytes.mean() / (avg_launch_ms * 1e-3) / 1e9)
+
+    detail = {}
+    for i, (s, m, _, _) in enumerate(pats):
+        detail.setdefault(f"{s}/{m}", []).append(texts[s].size / (launch_ms[i] * 1e-3) / 1e9)
+    detail = {k: round(float(np.median(v)), 1) for k, v in detail.items()}
+    if args.detail:
+        for k, v in detail.items():
+            log(f"  sigma/m {k:10s} median text GB/s {v:9.1f}")
+
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == args.workload:
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "hc_search_kernel", "avg_launch_us": round(avg_launch_ms * 1e3, 2),
+                "alg_bytes_per_launch": round(float(alg_bytes.mean()))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import hc_oracle as O
+
+        th = O.default_threads()
+        sample = []
+        seen = set()
+        for (s, m, off, x) in pats:
+            key = (s, m)
+            if sum(1 for k in seen if k[:2] == key) < args.cpu_sample_patterns:
+                seen.add((s, m, off))
+                sample.append((s, m, x))
+        t1 = time.perf_counter()
+        nbytes = 0
+        for s, m, x in sample:
+            O.count(x, texts[s], threads=th)
+            nbytes += texts[s].size
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": th, "kind": "oracle",
+               "sample": f"{len(sample)} patterns (1 per sigma and m), each over its full "
+                         f"{args.text_mib} MiB text, {dt:.1f} s"}
+
+    rec = {
+        "metric": "text GB/s per pattern (HC vs batched) + % HBM peak; p50/p99 search latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": workload, "launches_per_step": len(pats),
+                   "text_bytes_per_step": text_bytes, "occurrences_per_step": int(cnt.sum()),
+                   "wall_s": round(wall, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail_median_text_gbps": detail,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * hc.h -- C ABI of libhc: the searching phase of the Hash Chain (HC) exact
+ * string-matching algorithm (Palmer, Faro, Scafiti, "Efficient Online String
+ * Matching through Linked Weak Factors") on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 1; notation of Section 2): given a pattern x[0..m-1] and a
+ * text y[0..n-1] over bytes, report every start t, 0 <= t <= n-m, with
+ * y[t..t+m-1] = x. Characters are unsigned 8-bit values. Results are
+ * ascending int64 start positions, overlapping occurrences included, no
+ * duplicates. The set never depends on q, alpha, w or the launch shape.
+ *
+ * Conventions for every call:
+ *   - Nothing aborts or throws across this boundary; every call returns an
+ *     hc_status (hc_strerror() names it).
+ *   - "d_" pointers are device pointers on the current HIP device; all other
+ *     pointers are host pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is ordered on that stream; calls on one stream serialise,
+ *     calls on different streams may run concurrently.
+ *   - The caller owns every text and output buffer and keeps device buffers
+ *     alive until the stream work that uses them has finished.
+ *   - Text lengths are limited to n <= 2^32 - 1 bytes per text.
+ *   - HC_EHIP reports a failed HIP runtime call or a device that is not
+ *     gfx950; HC_ENOMEM a failed allocation.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HC_OK = 0,
+    HC_EINVAL = -1,     /* invalid argument; nothing was written            */
+    HC_ENOMEM = -2,     /* host or device allocation failed                  */
+    HC_EOVERFLOW = -3,  /* more results than `cap`; the true total is
+                           reported and the first `cap` results are written  */
+    HC_EAGAIN = -4,     /* served request not finished yet                   */
+    HC_EHIP = -5        /* HIP runtime error, or no gfx950 device            */
+} hc_status;
+
+/*
+ * Method parameters (Section 3.2; Section 4 explores 1 <= q <= 8 and
+ * 8 <= alpha <= 12). A field set to 0 is chosen by the library.
+ *   q      q-gram length, 1 <= q <= min(m, 8).
+ *   alpha  F has 2^alpha words (the hash h is reduced mod 2^alpha, eq. (3)).
+ *   w      bits per word of F, one of 8, 16, 32, 64 (the link hash of eq. (5)
+ *          maps a hash v to bit v mod w). Limits: 1 <= alpha and
+ *          2^alpha * w / 8 <= 64 KiB.
+ */
+typedef struct {
+    int32_t q;
+    int32_t alpha;
+    int32_t w;
+} hc_params;
+
+/* Work split inside the search kernel (no effect on results).
+ *   segment   each lane runs the search loop over its own block of window
+ *             starts (any split of the starts is exact, because every shift
+ *             only skips windows that cannot match, Section 3.3);
+ *   wave      the 64 lanes of a wavefront try 64 consecutive windows and the
+ *             wavefront moves on to the furthest position any lane proved
+ *             safe (shift agreement across the wavefront). */
+enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2 };
+
+/* Searching-phase variant (no effect on results).
+ *   hc        the plain searching phase (Section 3.3);
+ *   sentinel  SHC (Section 3.4, third optimisation): a copy of x is placed
+ *             after each text tile in on-chip memory, so the loop over
+ *             empty words runs without a position test;
+ *   sparse    for long patterns: text is fetched from memory only in the
+ *             128-byte lines that hold q-grams the search actually reads,
+ *             instead of streaming every tile. */
+enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIANT_SPARSE = 3 };
+
+/* Launch shape of the search kernel. A field set to 0 is chosen by the
+ * library (the autotuner's cache, else built-in priors). */
+typedef struct {
+    int32_t segment;     /* window starts per lane; tile = 256 * segment     */
+    int32_t schedule;    /* HC_SCHED_*                                        */
+    int32_t variant;     /* HC_VARIANT_*                                      */
+    int32_t wg_per_cu;   /* resident workgroups per compute unit, 1..8        */
+} hc_launch;
+
+typedef struct hc_pattern hc_pattern;   /* opaque; immutable once built      */
+
+/*
+ * hc_preprocess -- the preprocessing phase (Section 3.1, eqs. (1)-(2);
+ * Section 3.4 first and second optimisations): builds the word vector F,
+ * the shift s = floor(alpha/q) (eq. (4)), the mask F' = 2^alpha - 1 and the
+ * chain-head hash H_v for pattern x[0..m-1] (host bytes, copied).
+ *   params  may be NULL (all fields chosen by the library).
+ *   *out    receives a pattern object owned by the caller, released with
+ *           hc_pattern_free(). It may be shared by threads and streams.
+ * Errors: m < 1 or m > 4096, q outside [1, min(m, 8)], w not in
+ * {8,16,32,64}, alpha outside [1, alpha_max(w)] -> HC_EINVAL.
+ * Host-only: no device is touched until the first search.
+ */
+hc_status hc_preprocess(const uint8_t *x, int64_t m, const hc_params *params,
+                        hc_pattern **out);
+
+/*
+ * hc_pattern_info -- read back what hc_preprocess built (for F-table parity
+ * checks). Any output pointer may be NULL. *F_host points at 2^alpha words
+ * stored as uint64_t (low w bits used), valid while the pattern lives;
+ * *F_words = 2^alpha.
+ */
+hc_status hc_pattern_info(const hc_pattern *p, hc_params *used, int32_t *s,
+                          uint32_t *mask, uint32_t *hv, const uint64_t **F_host,
+                          int64_t *F_words, int64_t *m);
+
+void hc_pattern_free(hc_pattern *p);
+
+/*
+ * hc_search -- the searching phase (Section 3.3): all occurrences of the
+ * pattern in d_y[0..n-1] (device bytes).
+ *   d_out   device int64 array of `cap` entries; receives the first
+ *           min(count, cap) occurrences, ascending.
+ *   *count  (host) the true number of occurrences.
+ * Synchronises `stream` to read the count. count > cap -> HC_EOVERFLOW with
+ * the first `cap` results written. n < m -> HC_OK, count 0.
+ */
+hc_status hc_search(const hc_pattern *p, const uint8_t *d_y, int64_t n,
+                    int64_t *d_out, int64_t cap, int64_t *count, void *stream);
+
+/*
+ * hc_search_async -- as hc_search, without a host synchronisation: the total
+ * is written to *d_count (device int64) in stream order, and positions past
+ * `cap` are dropped without an error (compare *d_count with cap afterwards).
+ *   launch  may be NULL (library choice).
+ * A total of -1 in *d_count reports a launch that could not complete its
+ * ordered output (a tile's predecessors never published; not expected).
+ */
+hc_status hc_search_async(const hc_pattern *p, const uint8_t *d_y, int64_t n,
+                          int64_t *d_out, int64_t cap, int64_t *d_count,
+                          const hc_launch *launch, void *stream);
+
+/*
+ * Batched search: every listed (pattern, text) pair in one persistent launch
+ * (one text tile is staged on chip once and searched for many patterns).
+ *   d_text            device bytes holding all texts;
+ *   text_off[k]       (host) byte offset of text k in d_text, n_texts + 1
+ *                     entries, non-decreasing;
+ *   pat / pat_off     (host) all pattern bytes and n_pats + 1 offsets;
+ *   pair_pat/pair_text (host) pattern and text index of each of n_pairs pairs.
+ * Result (CSR, device): the occurrences of pair k are
+ * d_pos[d_pair_off[k] .. d_pair_off[k+1]) ascending; d_pair_off has
+ * n_pairs + 1 entries. *total (host) = all occurrences. total > cap ->
+ * HC_EOVERFLOW; then d_pair_off still holds the full offsets but d_pos holds
+ * only positions whose slot is < cap. Synchronises `stream`.
+ *   params  NULL = chosen per pattern length by the autotuner / priors.
+ */
+typedef struct {
+    const uint8_t *d_text;
+    const int64_t *text_off;
+    int32_t n_texts;
+    const uint8_t *pat;
+    const int64_t *pat_off;
+    int32_t n_pats;
+    const int32_t *pair_pat;
+    const int32_t *pair_text;
+    int64_t n_pairs;
+} hc_batch;
+
+hc_status hc_search_batched(const hc_batch *batch, const hc_params *params,
+                            int64_t *d_pos, int64_t cap, int64_t *d_pair_off,
+                            int64_t *total, void *stream);
+
+/*
+ * Serving: continuous batching of search requests against resident texts.
+ * hc_serve_create registers n_texts device texts (caller-owned, must outlive
+ * the server), a device-memory budget in bytes for in-flight requests
+ * (pattern tables plus result slots), and optional fixed params (NULL =
+ * library choice). A scheduler thread admits queued requests while the
+ * budget allows, groups the active requests by text, and scans each text in
+ * chunks, so a request that arrives while others run joins at the next chunk
+ * and finishes after one full cycle over its text.
+ * hc_serve_submit copies x and returns a request id (thread-safe).
+ * hc_serve_poll waits up to timeout_us (0 = do not wait) and returns
+ * HC_EAGAIN while the request runs; when done it copies min(count, cap)
+ * ascending positions to host `out`, sets *count, releases the request and
+ * returns HC_OK (or HC_EOVERFLOW when count > cap, the request is still
+ * released). Stats: latency percentiles of completed requests (submit to
+ * completion) and aggregate text bytes searched per second of server time.
+ */
+typedef struct hc_server hc_server;
+
+hc_status hc_serve_create(const uint8_t *const *d_texts, const int64_t *n,
+                          int32_t n_texts, int64_t device_mem_budget,
+                          const hc_params *params, hc_server **out);
+hc_status hc_serve_submit(hc_server *s, int32_t text_id, const uint8_t *x,
+                          int64_t m, uint64_t *req_id);
+hc_status hc_serve_poll(hc_server *s, uint64_t req_id, int64_t *out, int64_t cap,
+                        int64_t *count, int32_t timeout_us);
+hc_status hc_serve_stats(hc_server *s, double *p50_us, double *p99_us,
+                         double *agg_gbps, int64_t *done);
+hc_status hc_serve_destroy(hc_server *s);
+
+const char *hc_strerror(hc_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HC_H */

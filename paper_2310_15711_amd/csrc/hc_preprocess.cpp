@@ -1,0 +1,97 @@
+// Preprocessing phase of HC (Section 3.1 and Section 3.2 of the paper), host.
+//
+// F has 2^alpha words of w bits. For every pair of adjacent, non-overlapping
+// q-grams u1 = x[i..i+q-1], u2 = x[i+q..i+2q-1] (0 <= i <= m-2q), the word
+// of u2 receives the link bit of u1: F[h(u2)] |= lambda(h(u1)) (eq. (1)).
+// After all links, each q-gram that starts in the first q positions and
+// whose word is still empty gets the word 1 (eq. (2) with the first
+// optimisation of Section 3.4: marks go last, and only into empty words).
+// H_v is the hash of the leftmost q-gram of the chain of q-grams that ends at
+// position m-1 (second optimisation of Section 3.4).
+//
+// The paper walks the q-gram chains one after another so that each q-gram is
+// hashed once. Here every q-gram hash is computed once into an array first
+// and the links are read from it; OR is order-independent, so F is the same.
+#include <algorithm>
+#include <cstring>
+
+#include "hc_internal.h"
+
+namespace hc {
+
+int alpha_max(int w) {
+    // 2^alpha * w / 8 <= 64 KiB
+    int a = 0;
+    while ((int64_t(1) << (a + 1)) * w / 8 <= kMaxTableBytes) ++a;
+    return a;
+}
+
+hc_status validate_params(int64_t m, int q, int alpha, int w) {
+    if (m < 1 || m > kMaxM) return HC_EINVAL;
+    if (q < 1 || q > kMaxQ || q > m) return HC_EINVAL;
+    if (w != 8 && w != 16 && w != 32 && w != 64) return HC_EINVAL;
+    if (alpha < 1 || alpha > alpha_max(w)) return HC_EINVAL;
+    return HC_OK;
+}
+
+// Built-in priors when the caller leaves a parameter at 0. Section 4 reports
+// the best variants HC(q, alpha) in the range q <= 8, 8 <= alpha <= 12: q
+// between 3 and 8 with alpha 11-12 for m >= 16, q = 3-4 for m = 8. Short
+// patterns need q <= m.
+void default_params(int64_t m, int &q, int &alpha, int &w) {
+    if (q == 0) {
+        if (m <= 2) q = 1;
+        else if (m <= 4) q = 2;
+        else if (m <= 8) q = 3;
+        else if (m <= 16) q = 4;
+        else if (m <= 256) q = 5;
+        else q = 6;
+        q = int(std::min<int64_t>(q, m));
+    }
+    if (w == 0) w = 32;
+    if (alpha == 0) alpha = std::min(12, alpha_max(w));
+}
+
+static inline uint32_t qgram_hash(const uint8_t *u, int q, int s, uint32_t mask) {
+    // equation (3): the k-th character of the q-gram carries weight 2^(s*k);
+    // uint32 arithmetic wraps mod 2^32, which 2^alpha divides
+    uint32_t v = 0;
+    for (int k = q - 1; k >= 0; --k) v = (v << s) + u[k];
+    return v & mask;
+}
+
+void build_link_table(const uint8_t *x, int64_t m, int q, int alpha, int w,
+                      PatternData &out) {
+    out.x.assign(x, x + m);
+    out.m = m;
+    out.q = q;
+    out.alpha = alpha;
+    out.w = w;
+    out.s = alpha / q;                                  // eq. (4)
+    out.mask = uint32_t((uint64_t(1) << alpha) - 1);    // F' = 2^alpha - 1
+    out.F.assign(size_t(1) << alpha, 0);
+
+    const int64_t grams = m - q + 1;
+    std::vector<uint32_t> h(grams);
+    for (int64_t i = 0; i < grams; ++i) h[i] = qgram_hash(x + i, q, out.s, out.mask);
+
+    const uint32_t wmask = uint32_t(w - 1);
+    for (int64_t i = 0; i + 2 * q <= m; ++i)            // eq. (1)
+        out.F[h[i + q]] |= uint64_t(1) << (h[i] & wmask);
+    for (int64_t i = 0; i < std::min<int64_t>(q, grams); ++i)   // eq. (2), empty words only
+        if (out.F[h[i]] == 0) out.F[h[i]] = 1;
+
+    out.hv = h[(m - q) % q];   // leftmost q-gram of the chain ending at m-1
+}
+
+std::vector<uint8_t> pack_table(const PatternData &p) {
+    const size_t words = p.F.size(), bytes = size_t(p.w / 8);
+    std::vector<uint8_t> out(words * bytes);
+    for (size_t i = 0; i < words; ++i) {
+        uint64_t v = p.F[i];
+        std::memcpy(out.data() + i * bytes, &v, bytes);   // little-endian low bytes
+    }
+    return out;
+}
+
+}  // namespace hc

@@ -1,0 +1,50 @@
+// Host runtime of libhc: device checks, per-stream launch workspaces, lazy
+// upload of pattern tables, and the launchers behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hc_internal.h"
+
+namespace hc {
+
+struct DeviceInfo {
+    int device = -1;
+    int cus = 0;
+    uint32_t max_lds_per_block = 0;
+    uint32_t lds_per_cu = 0;
+    bool ok = false;   // gfx950
+};
+
+// Info for the current device (cached per device id).
+const DeviceInfo &device_info();
+
+// Launch workspace of one (device, stream): tile status words for the
+// ordered compaction and a control block. Calls on one stream serialise, so
+// one workspace per stream is never used by two launches at once.
+struct Workspace {
+    uint64_t *status = nullptr;
+    uint32_t status_cap = 0;
+    void *ctl = nullptr;   // hc::Ctl
+};
+
+hc_status workspace_for(hipStream_t stream, uint32_t tiles, Workspace **out);
+
+// Device copies of a pattern's F (packed w-bit words) and x on the current device.
+hc_status pattern_on_device(hc_pattern *p, const DeviceCopy **out);
+
+hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
+                        int64_t *d_out, int64_t cap, int64_t *d_count, const hc_launch &lc,
+                        hipStream_t stream);
+
+// Launch shape chosen for a pattern when the caller leaves fields at 0.
+hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req);
+
+#define HC_CHECK_HIP(expr)                       \
+    do {                                         \
+        if ((expr) != hipSuccess) return HC_EHIP; \
+    } while (0)
+
+}  // namespace hc

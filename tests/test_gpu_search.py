@@ -1,0 +1,239 @@
+"""GPU parity of the single-pattern searching phase (hc_search through the C
+ABI) against the oracle's brute force: element-by-element equality of the
+occurrence lists (integer results, so bit-exact)."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import golden_lines
+from oracle import hc_oracle as O
+from paper_2310_15711_amd import binding as B
+from paper_2310_15711_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def to_dev(y_np, dev):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(y_np)).to(dev)
+
+
+def gpu_occ(x, y_dev, params=None, launch=None, cap=None):
+    """Occurrences via hc_search_async + explicit capacity; returns numpy."""
+    import torch
+
+    p = B.hc_preprocess(x, params)
+    n = int(y_dev.numel())
+    if cap is None:
+        cap = max(1, n)
+    out = torch.empty(max(cap, 1), dtype=torch.int64, device=y_dev.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=y_dev.device)
+    if n < len(x):
+        st, c = B.hc_search(p, y_dev, out)
+        return out[:0].cpu().numpy(), c
+    B.hc_search_async(p, y_dev, out, cnt, launch=launch)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    return out[:min(c, cap)].cpu().numpy(), c
+
+
+def test_hand_cases(torch_dev):
+    for xh, yh, occ in golden_lines("hand_cases.txt"):
+        x, y = bytes.fromhex(xh), bytes.fromhex(yh)
+        want = [] if occ == "-" else [int(t) for t in occ.split(",")]
+        announce("hand", xh, yh)
+        yd = to_dev(np.frombuffer(y, dtype=np.uint8), torch_dev)
+        p = B.hc_preprocess(x)
+        got = B.find_all(p, yd).cpu().tolist()
+        assert got == want, (xh, yh)
+
+
+SCHEDS = [B.HC_SCHED_SEGMENT, B.HC_SCHED_WAVE]
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_random_against_oracle(torch_dev, sched):
+    g = random.Random(2024 + sched)
+    for case in range(160):
+        sigma = g.choice([2, 4, 20, 64, 256])
+        n = g.choice([g.randint(0, 3000), g.randint(3000, 200000)])
+        m = g.choice([g.randint(1, 12), g.randint(12, 300), g.randint(300, 1200)])
+        alphabet = np.array(g.sample(range(256), sigma), dtype=np.uint8)
+        rs = np.random.default_rng(case * 7 + sched)
+        y = alphabet[rs.integers(0, sigma, size=n)]
+        if n >= m and g.random() < 0.8:
+            t = g.randint(0, n - m)
+            x = y[t:t + m].tobytes()
+            for _ in range(g.randint(0, 5)):          # plant a few more copies
+                u = g.randint(0, n - m)
+                y[u:u + m] = np.frombuffer(x, dtype=np.uint8)
+        else:
+            x = alphabet[rs.integers(0, sigma, size=m)].tobytes()
+        q = g.randint(1, min(m, 8))
+        w = g.choice([8, 16, 32, 64])
+        alpha = g.randint(1, {8: 16, 16: 15, 32: 14, 64: 13}[w])
+        seg = g.choice([8, 12, 36, 132, 200])
+        announce("random", sched, case, f"n={n} m={m} sigma={sigma} q={q} a={alpha} w={w} seg={seg}")
+        yd = to_dev(y, torch_dev)
+        got, c = gpu_occ(x, yd, (q, alpha, w), (seg, sched, 0, 0))
+        want = O.occurrences(x, y)
+        assert c == len(want)
+        assert np.array_equal(got, want), (case, n, m, q, alpha, w, seg)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_planted_config(torch_dev, sched):
+    p = W.planted_config()
+    announce("planted", sched)
+    yd = to_dev(p.y, torch_dev)
+    got, c = gpu_occ(p.x, yd, None, (0, sched, 0, 0))
+    want = O.occurrences(p.x, p.y)
+    assert np.array_equal(got, want)
+    assert set(p.plants) | {p.source} <= set(got.tolist())
+    assert len(got) >= 101
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_closed_forms(torch_dev, sched):
+    n = 100_000
+    ya = np.full(n, ord("a"), dtype=np.uint8)
+    yd = to_dev(ya, torch_dev)
+    for m in (1, 2, 7, 8, 33, 500):
+        for q in sorted({1, min(m, 3), min(m, 8)}):
+            announce("a^n", sched, m, q)
+            got, c = gpu_occ(b"a" * m, yd, (q, 10, 32), (36, sched, 0, 0))
+            assert c == n - m + 1
+            assert np.array_equal(got, np.arange(n - m + 1))
+    yab = np.frombuffer(b"ab" * (n // 2), dtype=np.uint8)
+    yd = to_dev(yab, torch_dev)
+    for k in (1, 3, 40):
+        announce("(ab)^N", sched, k)
+        got, c = gpu_occ(b"ab" * k, yd, None, (36, sched, 0, 0))
+        assert np.array_equal(got, np.arange(0, n - 2 * k + 1, 2))
+
+
+def test_overflow_reports_total_and_prefix(torch_dev):
+    import torch
+
+    n = 50_000
+    yd = to_dev(np.full(n, 7, dtype=np.uint8), torch_dev)
+    p = B.hc_preprocess(bytes([7, 7]))
+    out = torch.full((1000,), -1, dtype=torch.int64, device=torch_dev)
+    announce("overflow")
+    st, c = B.hc_search(p, yd, out)
+    assert st == B.HC_EOVERFLOW and c == n - 1
+    assert np.array_equal(out.cpu().numpy(), np.arange(1000))
+    # capacity 0: count only
+    empty = torch.empty(0, dtype=torch.int64, device=torch_dev)
+    st, c = B.hc_search(p, yd, empty)
+    assert st == B.HC_EOVERFLOW and c == n - 1
+
+
+def test_edges(torch_dev):
+    import torch
+
+    announce("edges")
+    p = B.hc_preprocess(b"abc")
+    out = torch.empty(16, dtype=torch.int64, device=torch_dev)
+    for y in (b"", b"a", b"ab"):
+        yd = torch.tensor(list(y), dtype=torch.uint8, device=torch_dev)
+        assert B.hc_search(p, yd, out) == (B.HC_OK, 0)
+    yd = torch.tensor(list(b"abc"), dtype=torch.uint8, device=torch_dev)
+    assert B.hc_search(p, yd, out) == (B.HC_OK, 1) and int(out[0]) == 0
+    # m = 1, every byte value
+    y = np.arange(256, dtype=np.uint8).repeat(3)
+    yd = to_dev(y, torch_dev)
+    for b in (0, 1, 127, 128, 255):
+        got, c = gpu_occ(bytes([b]), yd)
+        assert got.tolist() == [3 * b, 3 * b + 1, 3 * b + 2]
+
+
+def test_misaligned_text_pointers(torch_dev):
+    g = np.random.default_rng(5)
+    base = g.integers(0, 4, size=70_000, dtype=np.uint8) + ord("A")
+    x = base[1234:1234 + 20].tobytes()
+    bd = to_dev(base, torch_dev)
+    for off in range(0, 17):
+        for tail in (0, 1, 5, 15):
+            announce("misaligned", off, tail)
+            view = bd[off:bd.numel() - tail]
+            got, c = gpu_occ(x, view, None, (12, 1, 0, 0))
+            want = O.occurrences(x, base[off:base.size - tail])
+            assert np.array_equal(got, want)
+
+
+def test_parameter_invariance(torch_dev):
+    y = W.markov_text(300_000, cfg=W.TEST_CFG)
+    rs = np.random.default_rng(9)
+    for m in (3, 16, 64, 257):
+        t = int(rs.integers(0, y.size - m))
+        x = y[t:t + m].tobytes()
+        want = O.occurrences(x, y)
+        yd = to_dev(y, torch_dev)
+        for q in sorted({1, 2, min(m, 4), min(m, 8)}):
+            for alpha, w in ((4, 8), (11, 16), (12, 32), (13, 64)):
+                for seg, sched in ((16, 1), (132, 1), (64, 2)):
+                    announce("invariance", m, q, alpha, w, seg, sched)
+                    got, c = gpu_occ(x, yd, (q, alpha, w), (seg, sched, 0, 0))
+                    assert np.array_equal(got, want), (m, q, alpha, w, seg, sched)
+
+
+def test_repeated_launches_and_streams(torch_dev):
+    import torch
+
+    rs = np.random.default_rng(3)
+    y = (rs.integers(0, 4, size=2_000_000, dtype=np.uint8) + 65)
+    yd = to_dev(y, torch_dev)
+    x = y[777:777 + 6].tobytes()
+    want = O.occurrences(x, y)
+    p = B.hc_preprocess(x)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for i in range(40):
+        s = (s1, s2, None)[i % 3]
+        n = int(rs.integers(1, y.size))
+        out = torch.empty(n, dtype=torch.int64, device=torch_dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=torch_dev)
+        announce("repeat", i, n)
+        B.hc_search_async(p, yd[:n], out, cnt, launch=(int(rs.choice([8, 36, 132])), 1, 0, 0),
+                          stream=s)
+        outs.append((n, out, cnt))
+    torch.cuda.synchronize()
+    for n, out, cnt in outs:
+        w = want[want <= n - 6]
+        assert int(cnt.item()) == w.size
+        assert np.array_equal(out[:w.size].cpu().numpy(), w)
+
+
+@pytest.mark.parametrize("sigma", [4, 20, 64])
+def test_full_size_sampled(torch_dev, sigma):
+    """The full 256 MiB single-pattern texts, launch shape as benchmarked,
+    two sampled patterns per length, complete lists compared."""
+    import torch
+
+    y = W.single_text(sigma)
+    yd = to_dev(y, torch_dev)
+    for m in W.SINGLE_LENGTHS:
+        for off, x in W.single_patterns(y, sigma, m, count=2):
+            announce("full", sigma, m, off)
+            want = O.occurrences(x, y)
+            got, c = gpu_occ(x, yd, None, None, cap=int(want.size) + 16)
+            assert c == want.size
+            assert np.array_equal(got, want), (sigma, m, off)
+    del yd
+    torch.cuda.empty_cache()
