@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--segment", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--params", default=None, help="q,alpha,w for every pattern")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patterns", type=int, default=1,
@@ -102,7 +103,7 @@ def main():
     dtexts = {s: torch.from_numpy(y).to(dev) for s, y in texts.items()}
     params = tuple(int(v) for v in args.params.split(",")) if args.params else None
     handles = [B.hc_preprocess(x, params) for (_, _, _, x) in pats]
-    launch = (args.segment, args.schedule, args.variant, 0)
+    launch = (args.segment, args.schedule, args.variant, args.wg_per_cu)
     cap = 1 << 25
     out = torch.empty(cap, dtype=torch.int64, device=dev)
     counts = torch.zeros(len(pats), dtype=torch.int64, device=dev)

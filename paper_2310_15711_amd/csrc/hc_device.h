@@ -16,6 +16,16 @@ constexpr int kWave = 64;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Workgroup barrier that orders LDS only. A plain __syncthreads() also waits
+// for every outstanding global load (vmcnt(0) on gfx9), which would drain the
+// prefetch of the next tile at each barrier; all cross-wave data here goes
+// through LDS, so the LDS-scoped fences are sufficient.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ----------------------------------------------------------------------------
 // LDS layout of one workgroup (bytes, every region 16-byte aligned)
 // ----------------------------------------------------------------------------
@@ -39,13 +49,13 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t tile, uint32_t m, uint3
                                                 uint32_t extra) {
     LdsLayout L;
     L.text_off = 0;
-    L.text_bytes = 16u + 16u * chunks_for(tile + m - 1u) + align16(extra) + 16u;
+    L.text_bytes = 16u + 16u * chunks_for(tile + m - 1u) + align16(extra) + 32u;
     L.bitmap_off = L.text_off + L.text_bytes;
     L.bitmap_bytes = align16(tile / 8u);
     L.table_off = L.bitmap_off + L.bitmap_bytes;
     L.table_bytes = align16(table_bytes);
     L.x_off = L.table_off + L.table_bytes;
-    L.x_bytes = align16(m) + 16u;
+    L.x_bytes = align16(m) + 32u;
     L.misc_off = L.x_off + L.x_bytes;
     L.misc_bytes = 128u;
     L.total = L.misc_off + L.misc_bytes;
@@ -92,11 +102,33 @@ __device__ __forceinline__ bool linked(WT z, uint32_t v) {
     return (z >> (v & (wbits - 1u))) & 1u;
 }
 
-// Compare the m bytes at LDS byte position a of the text with x (LDS).
-__device__ __forceinline__ bool window_equals(const uint8_t *__restrict__ t8, uint32_t a,
-                                              const uint8_t *__restrict__ x8, uint32_t m) {
-    for (uint32_t k = 0; k < m; ++k)
-        if (t8[a + k] != x8[k]) return false;
+// Compare the m bytes at LDS byte position a of the text with x (LDS, 16-byte
+// aligned and padded). Four bytes per step with sixteen bytes of each side
+// in flight; bytes read past either end (within the LDS padding) are masked.
+__device__ __forceinline__ bool window_equals(const uint32_t *__restrict__ t32, uint32_t a,
+                                              const uint32_t *__restrict__ x32, uint32_t m) {
+    const uint32_t sh = a & 3u, base = a >> 2;
+    const uint32_t nw = (m + 3u) >> 2;
+    const uint32_t tail = (m & 3u) ? ((1u << (8u * (m & 3u))) - 1u) : 0xFFFFFFFFu;
+    uint32_t lo = t32[base];
+    for (uint32_t i = 0; i < nw; i += 4) {
+        uint32_t d[4], xw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            d[j] = t32[base + i + j + 1];
+            xw[j] = x32[i + j];
+        }
+        uint32_t diff = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t w = __builtin_amdgcn_alignbyte(d[j], j == 0 ? lo : d[j - 1], sh);
+            uint32_t dj = w ^ xw[j];
+            if (i + j + 1 == nw) dj &= tail;
+            if (i + j < nw) diff |= dj;
+        }
+        if (diff) return false;
+        lo = d[3];
+    }
     return true;
 }
 
@@ -106,19 +138,17 @@ struct PatternView {
 };
 
 // One attempt of the searching phase at window end J (LDS byte position of
-// the window's last character is tb + J). Returns the next window end. When
-// every q-gram of the window links and the last hash equals H_v, the window
-// is compared with x and, if equal, *hit is set.
+// the window's last character is tb + J), given the hash v of the q-gram that
+// ends at J and its word z = F[v] != 0. Follows the chain of q-grams ending
+// at J - q, J - 2q, ... while they stay inside the window; each must carry
+// its link bit in the word of the q-gram after it. Returns the next window
+// end. When every q-gram links and the last hash equals H_v, *hit is set: the
+// window is a candidate, compared with x in a later pass.
 template <int Q, typename WT>
-__device__ __forceinline__ uint32_t hc_attempt(const uint32_t *__restrict__ t32,
-                                               const uint8_t *__restrict__ t8, uint32_t tb,
-                                               const WT *__restrict__ F,
-                                               const uint8_t *__restrict__ x8,
-                                               const PatternView &P, uint32_t J, bool *hit) {
-    uint32_t v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
-    WT z = F[v];
+__device__ __forceinline__ uint32_t hc_chain(const uint32_t *__restrict__ t32, uint32_t tb,
+                                             const WT *__restrict__ F, const PatternView &P,
+                                             uint32_t J, uint32_t v, WT z, bool *hit) {
     const uint32_t shift = P.m - Q + 1u;
-    if (z == 0) return J + shift;            // no q-gram of x hashes here
     int32_t e = int32_t(J);
     const int32_t lo = int32_t(J) - int32_t(P.m) + 2 * Q;
     while (e >= lo) {                        // a whole q-gram still fits before e
@@ -128,34 +158,63 @@ __device__ __forceinline__ uint32_t hc_attempt(const uint32_t *__restrict__ t32,
         z = F[v];
     }
     // every q-gram of the window is linked: candidate
-    if (v == P.hv && window_equals(t8, tb + J + 1u - P.m, x8, P.m)) *hit = true;
+    if (v == P.hv) *hit = true;
     return J + 1u;
 }
 
-// Searching loop over window ends [jlo, jhi) (tile-relative), one lane.
-// Marks the start of each occurrence in the tile bitmap.
 template <int Q, typename WT>
-__device__ __forceinline__ void hc_segment(const uint32_t *__restrict__ t32,
-                                           const uint8_t *__restrict__ t8, uint32_t tb,
-                                           const WT *__restrict__ F,
-                                           const uint8_t *__restrict__ x8, const PatternView &P,
-                                           uint32_t jlo, uint32_t jhi, uint32_t *bitmap) {
-    uint32_t J = jlo;
+__device__ __forceinline__ uint32_t hc_attempt(const uint32_t *__restrict__ t32, uint32_t tb,
+                                               const WT *__restrict__ F, const PatternView &P,
+                                               uint32_t J, bool *hit) {
+    const uint32_t v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
+    const WT z = F[v];
+    if (z == 0) return J + P.m - Q + 1u;     // no q-gram of x hashes here
+    return hc_chain<Q, WT>(t32, tb, F, P, J, v, z, hit);
+}
+
+__device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t st, uint32_t *any) {
+    atomicOr(&bitmap[st >> 5], 1u << (st & 31u));
+    *any = 1u;
+}
+
+// Searching loop over window ends [jlo, jhi) (tile-relative), one lane.
+// The range is split in two halves searched side by side, so that the LDS
+// round trips of two independent attempts overlap. Marks the start of each
+// candidate window in the tile bitmap and sets *any.
+template <int Q, typename WT>
+__device__ __forceinline__ void hc_segment(const uint32_t *__restrict__ t32, uint32_t tb,
+                                           const WT *__restrict__ F, const PatternView &P,
+                                           uint32_t jlo, uint32_t jhi, uint32_t *bitmap,
+                                           uint32_t *any) {
     const uint32_t shift = P.m - Q + 1u;
-    while (J < jhi) {
-        // fast path: empty word, shift by m - q + 1
-        const uint32_t v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
-        if (F[v] == 0) {
-            J += shift;
-            continue;
+    const uint32_t jmid = jlo + ((jhi - jlo) >> 1);
+    uint32_t J0 = jlo, J1 = jmid;
+    while (J0 < jmid || J1 < jhi) {
+        // a finished half re-reads its first window (in the tile), unused
+        const uint32_t a0 = J0 < jmid ? J0 : jlo, a1 = J1 < jhi ? J1 : jlo;
+        const uint32_t v0 = qgram_hash<Q>(t32, tb + a0, P.s, P.mask);
+        const uint32_t v1 = qgram_hash<Q>(t32, tb + a1, P.s, P.mask);
+        const WT z0 = F[v0], z1 = F[v1];
+        if (J0 < jmid) {
+            if (z0 == 0) {
+                J0 += shift;                     // empty word: shift by m - q + 1
+            } else {
+                bool hit = false;
+                const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J0, v0, z0, &hit);
+                if (hit) mark(bitmap, J0 + 1u - P.m, any);
+                J0 = next;
+            }
         }
-        bool hit = false;
-        const uint32_t next = hc_attempt<Q, WT>(t32, t8, tb, F, x8, P, J, &hit);
-        if (hit) {
-            const uint32_t st = J + 1u - P.m;
-            atomicOr(&bitmap[st >> 5], 1u << (st & 31u));
+        if (J1 < jhi) {
+            if (z1 == 0) {
+                J1 += shift;
+            } else {
+                bool hit = false;
+                const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J1, v1, z1, &hit);
+                if (hit) mark(bitmap, J1 + 1u - P.m, any);
+                J1 = next;
+            }
         }
-        J = next;
     }
 }
 
@@ -164,11 +223,10 @@ __device__ __forceinline__ void hc_segment(const uint32_t *__restrict__ t32,
 // starts strictly between its own start and the start of its next window,
 // so the wavefront may continue from the furthest such start (or 64 on).
 template <int Q, typename WT>
-__device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32,
-                                        const uint8_t *__restrict__ t8, uint32_t tb,
-                                        const WT *__restrict__ F, const uint8_t *__restrict__ x8,
-                                        const PatternView &P, uint32_t slo, uint32_t shi,
-                                        uint32_t *bitmap, uint32_t lane) {
+__device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32, uint32_t tb,
+                                        const WT *__restrict__ F, const PatternView &P,
+                                        uint32_t slo, uint32_t shi, uint32_t *bitmap,
+                                        uint32_t lane, uint32_t *any) {
     uint32_t base = slo;
     while (base < shi) {
         const uint32_t st = base + lane;
@@ -176,8 +234,8 @@ __device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32,
         if (st < shi) {
             bool hit = false;
             const uint32_t J = st + P.m - 1u;
-            const uint32_t nJ = hc_attempt<Q, WT>(t32, t8, tb, F, x8, P, J, &hit);
-            if (hit) atomicOr(&bitmap[st >> 5], 1u << (st & 31u));
+            const uint32_t nJ = hc_attempt<Q, WT>(t32, tb, F, P, J, &hit);
+            if (hit) mark(bitmap, st, any);
             next_start = nJ + 1u - P.m;
         }
         uint32_t far = next_start;
@@ -187,153 +245,77 @@ __device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32,
     }
 }
 
-// ----------------------------------------------------------------------------
-// Tile status words for the single-pass ordered compaction (decoupled
-// look-back): [63:62] flag (1 = tile count, 2 = inclusive prefix),
-// [61:32] launch generation, [31:0] value.
-// ----------------------------------------------------------------------------
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagPre = 2ull << 62;
-constexpr uint32_t kGenMask = 0x3FFFFFFFu;
+// Staging of text bytes [g0, g1) into LDS as aligned 16-byte chunks, in two
+// halves so that the loads of the next tile are in flight while the current
+// tile is searched: stage_issue() loads into registers, stage_commit() stores
+// them to LDS. Byte g0 lands at LDS text position 16 + ((uintptr)(y + g0) & 15)
+// (returned by stage_issue). Every chunk read holds at least one byte of
+// [g0, g1), so no read leaves the pages that hold the text.
+constexpr int kStageMax = 10;   // chunks per thread: (tile + m - 1) <= 16 * 256 * kStageMax - 32
 
-__device__ __forceinline__ uint64_t status_word(uint64_t flag, uint32_t gen, uint32_t value) {
-    return flag | (uint64_t(gen & kGenMask) << 32) | value;
-}
-
-__device__ __forceinline__ uint64_t load_agent(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_agent(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Polls of a predecessor's status before a look-back gives up (about a
-// minute): every wait then ends, and the launch reports an error instead of
-// hanging.
-constexpr uint32_t kSpinLimit = 1u << 26;
-
-// Exclusive prefix of tile `t` given its own count; run by one whole
-// wavefront. Publishes the tile's count, then its inclusive prefix. Sets
-// *err when a predecessor never published.
-__device__ inline uint32_t lookback(uint64_t *status, uint32_t t, uint32_t gen, uint32_t count,
-                                    uint32_t lane, uint32_t *err) {
-    if (t == 0) {
-        if (lane == 0) store_agent(&status[0], status_word(kFlagPre, gen, count));
-        return 0;
-    }
-    if (lane == 0) store_agent(&status[t], status_word(kFlagAgg, gen, count));
-    uint32_t excl = 0;
-    int64_t k = int64_t(t) - 1;
-    uint32_t spins = 0;
-    while (true) {
-        const int64_t idx = k - int64_t(lane);
-        const uint64_t e = idx >= 0 ? load_agent(&status[idx]) : 0ull;
-        const uint32_t fl = uint32_t(e >> 62);
-        const bool valid = fl != 0 && uint32_t((e >> 32) & kGenMask) == (gen & kGenMask);
-        const uint64_t bpre = __ballot(valid && fl == 2);
-        const uint64_t binv = __ballot(!valid && idx >= 0);
-        const int p = bpre ? __ffsll((unsigned long long)bpre) - 1 : 64;
-        const uint64_t need = p >= 63 ? ~0ull : ((2ull << p) - 1ull);
-        if (binv & need) {
-            if (++spins > kSpinLimit) {
-                if (lane == 0) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        uint32_t val = (int(lane) <= p && idx >= 0) ? uint32_t(e) : 0u;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) val += (uint32_t)__shfl_xor((int)val, d, kWave);
-        excl += val;
-        if (p < 64) break;
-        k -= kWave;
-    }
-    if (lane == 0) store_agent(&status[t], status_word(kFlagPre, gen, excl + count));
-    return excl;
-}
-
-// Control block of one launch workspace (device memory, zero-initialised).
-struct Ctl {
-    uint32_t ticket;   // next tile ticket
-    uint32_t done;     // workgroups finished
-    uint32_t gen;      // launch generation
-    uint32_t err;      // a look-back gave up during this launch
+struct Stage {
+    u32x4 r[kStageMax];
+    uint32_t nch;
 };
 
-// Called by every workgroup (all threads) after its last tile: the last one to
-// finish resets the counters and advances the generation; on wrap-around the
-// status words are cleared so that no stale generation can match. A launch
-// whose look-back gave up reports a total of -1.
-__device__ inline void finish_launch(Ctl *ctl, uint64_t *status, uint32_t status_cap,
-                                     uint32_t gen, uint32_t *lds_flag, int64_t *d_total) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t d = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        *lds_flag = (d == gridDim.x - 1u) ? 1u : 0u;
+__host__ __device__ inline uint32_t stage_limit(uint32_t threads) {
+    return 16u * threads * uint32_t(kStageMax) - 32u;
+}
+
+typedef const __attribute__((address_space(1))) u32x4 global_u32x4;
+
+__device__ __forceinline__ uint32_t stage_issue(const uint8_t *y, uint64_t g0, uint64_t g1,
+                                                Stage &st) {
+    const uint8_t *a = y + g0;
+    const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(a) & 15u);
+    st.nch = (mis + uint32_t(g1 - g0) + 15u) >> 4;
+    // global address space: flat loads would also count against the LDS
+    // counter and make every LDS barrier wait for this prefetch
+    global_u32x4 *src = (global_u32x4 *)(a - mis);
+#pragma unroll
+    for (int k = 0; k < kStageMax; ++k) {
+        const uint32_t c = k * 256u + threadIdx.x;   // 256 threads per workgroup
+        if (c < st.nch) st.r[k] = __builtin_nontemporal_load(src + c);
     }
-    __syncthreads();
-    if (*lds_flag == 0u) return;
-    const uint32_t ng = (gen + 1u) & kGenMask;
-    if (ng == 0u) {
-        for (uint32_t i = threadIdx.x; i < status_cap; i += blockDim.x) store_agent(&status[i], 0ull);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (__hip_atomic_exchange(&ctl->err, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u &&
-            d_total)
-            *d_total = -1;
-        __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->gen, ng, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return 16u + mis;
+}
+
+__device__ __forceinline__ void stage_commit(const Stage &st, uint8_t *lds_text) {
+    u32x4 *dst = reinterpret_cast<u32x4 *>(lds_text + 16);
+#pragma unroll
+    for (int k = 0; k < kStageMax; ++k) {
+        const uint32_t c = k * 256u + threadIdx.x;   // 256 threads per workgroup
+        if (c < st.nch) dst[c] = st.r[k];
     }
 }
 
-// Stage bytes [g0, g1) of a text into LDS as aligned 16-byte chunks. Byte g0
-// lands at LDS text position 16 + ((uintptr)(y + g0) & 15); returns that
-// position. Every chunk read holds at least one byte of [g0, g1), so no read
-// leaves the pages that hold the text.
-__device__ __forceinline__ uint32_t stage_text(const uint8_t *y, uint64_t g0, uint64_t g1,
-                                               uint8_t *lds_text) {
-    const uintptr_t a0 = reinterpret_cast<uintptr_t>(y + g0);
-    const uintptr_t p0 = a0 & ~uintptr_t(15);
-    const uint32_t nch = uint32_t((reinterpret_cast<uintptr_t>(y + g1) - p0 + 15u) >> 4);
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(p0);
-    u32x4 *dst = reinterpret_cast<u32x4 *>(lds_text + 16);
-    constexpr int kUnroll = 8;
-    for (uint32_t base = 0; base < nch; base += kUnroll * blockDim.x) {
-        u32x4 r[kUnroll];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            const uint32_t c = base + k * blockDim.x + threadIdx.x;
-            if (c < nch) r[k] = __builtin_nontemporal_load(src + c);
-        }
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            const uint32_t c = base + k * blockDim.x + threadIdx.x;
-            if (c < nch) dst[c] = r[k];
-        }
-    }
-    return 16u + uint32_t(a0 - p0);
+// Inclusive prefix sum across a wavefront with DPP row shifts and row
+// broadcasts (no LDS round trips).
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+    // row_shr:1,2,4,8 within rows of 16 lanes (bound_ctrl: shifted-in lanes read 0)
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+    // row_bcast:15 adds the last lane of each row to the next row (rows 1, 3)
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    // row_bcast:31 adds lane 31 to rows 2 and 3
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return v;
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim = 256).
 // Returns the thread's exclusive prefix; *total receives the block sum.
+// lds_w holds four words; callers separate successive scans by a barrier.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t c, uint32_t *lds_w,
                                                          uint32_t *total) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    uint32_t incl = c;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = (uint32_t)__shfl_up((int)incl, d, kWave);
-        if (lane >= uint32_t(d)) incl += t;
-    }
+    const uint32_t incl = wave_inclusive_sum(c);
     if (lane == kWave - 1) lds_w[wid] = incl;
-    __syncthreads();
+    lds_barrier();
     uint32_t before = 0, all = 0;
-    const uint32_t nw = blockDim.x / kWave;
-    for (uint32_t i = 0; i < nw; ++i) {
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
         const uint32_t v = lds_w[i];
         if (i < wid) before += v;
         all += v;

@@ -21,16 +21,20 @@ struct DeviceInfo {
 // Info for the current device (cached per device id).
 const DeviceInfo &device_info();
 
-// Launch workspace of one (device, stream): tile status words for the
-// ordered compaction and a control block. Calls on one stream serialise, so
-// one workspace per stream is never used by two launches at once.
+// Launch workspace of one (device, stream): the grid-barrier control block and
+// per-tile results of the search phase (counts, short position slots, spilled
+// bitmaps). Calls on one stream serialise, so one workspace per stream is never
+// used by two launches at once.
 struct Workspace {
-    uint64_t *status = nullptr;
-    uint32_t status_cap = 0;
-    void *ctl = nullptr;   // hc::Ctl
+    void *ctl = nullptr;          // control words (work tickets), zero-initialised
+    uint32_t *counts = nullptr;   // tiles_cap entries
+    uint16_t *slots = nullptr;    // tiles_cap * 32 entries
+    uint32_t *spill = nullptr;    // spill_words_cap entries
+    uint32_t tiles_cap = 0;
+    uint64_t spill_words_cap = 0;
 };
 
-hc_status workspace_for(hipStream_t stream, uint32_t tiles, Workspace **out);
+hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out);
 
 // Device copies of a pattern's F (packed w-bit words) and x on the current device.
 hc_status pattern_on_device(hc_pattern *p, const DeviceCopy **out);

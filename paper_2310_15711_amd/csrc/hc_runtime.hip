@@ -34,7 +34,7 @@ const DeviceInfo &device_info() {
     return cache.emplace(dev, di).first->second;
 }
 
-hc_status workspace_for(hipStream_t stream, uint32_t tiles, Workspace **out) {
+hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out) {
     static std::mutex mu;
     static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> spaces;
     const DeviceInfo &di = device_info();
@@ -44,22 +44,35 @@ hc_status workspace_for(hipStream_t stream, uint32_t tiles, Workspace **out) {
     if (!slot) {
         slot.reset(new (std::nothrow) Workspace());
         if (!slot) return HC_ENOMEM;
-        if (hipMalloc(&slot->ctl, sizeof(Ctl)) != hipSuccess) return HC_ENOMEM;
-        HC_CHECK_HIP(hipMemset(slot->ctl, 0, sizeof(Ctl)));
+        if (hipMalloc(&slot->ctl, 64) != hipSuccess) return HC_ENOMEM;
+        HC_CHECK_HIP(hipMemset(slot->ctl, 0, 64));   // work tickets of dynamically dealt kernels
     }
     Workspace *ws = slot.get();
-    if (ws->status_cap < tiles) {
-        // earlier launches on this stream may still read the old array
+    const uint64_t spill_words = uint64_t(tiles) * (tile / 32u);
+    if (ws->tiles_cap < tiles || ws->spill_words_cap < spill_words) {
+        // earlier launches on this stream may still use the old buffers
         HC_CHECK_HIP(hipStreamSynchronize(stream));
-        if (ws->status) HC_CHECK_HIP(hipFree(ws->status));
-        ws->status = nullptr;
-        uint32_t cap = std::max<uint32_t>(tiles, 4096);
-        if (hipMalloc(reinterpret_cast<void **>(&ws->status), sizeof(uint64_t) * cap) != hipSuccess) {
-            ws->status_cap = 0;
-            return HC_ENOMEM;
+        if (ws->tiles_cap < tiles) {
+            (void)hipFree(ws->counts);
+            (void)hipFree(ws->slots);
+            ws->counts = nullptr;
+            ws->slots = nullptr;
+            ws->tiles_cap = 0;
+            const uint32_t cap = std::max<uint32_t>(tiles, 4096);
+            if (hipMalloc(reinterpret_cast<void **>(&ws->counts), sizeof(uint32_t) * cap) != hipSuccess ||
+                hipMalloc(reinterpret_cast<void **>(&ws->slots), sizeof(uint16_t) * 32u * cap) != hipSuccess)
+                return HC_ENOMEM;
+            ws->tiles_cap = cap;
         }
-        HC_CHECK_HIP(hipMemset(ws->status, 0, sizeof(uint64_t) * cap));
-        ws->status_cap = cap;
+        if (ws->spill_words_cap < spill_words) {
+            (void)hipFree(ws->spill);
+            ws->spill = nullptr;
+            ws->spill_words_cap = 0;
+            const uint64_t cap = std::max<uint64_t>(spill_words, 1u << 20);
+            if (hipMalloc(reinterpret_cast<void **>(&ws->spill), sizeof(uint32_t) * cap) != hipSuccess)
+                return HC_ENOMEM;
+            ws->spill_words_cap = cap;
+        }
     }
     *out = ws;
     return HC_OK;

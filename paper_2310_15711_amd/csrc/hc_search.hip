@@ -1,11 +1,17 @@
 // Single-pattern searching phase of HC (Section 3.3) on gfx950.
 //
-// One persistent workgroup per slot on the chip takes text tiles in ticket
-// order. Per tile it stages the window starts' bytes (tile plus an (m-1)-byte
-// halo) from HBM into LDS with 16-byte loads, runs the searching loop in every
-// lane against F and x held in LDS for the whole launch, marks occurrences in
-// an LDS bitmap, and writes them as ascending int64 positions at an offset
-// found by decoupled look-back over the preceding tiles.
+// Two launches on the caller's stream:
+//  1. hc_search_kernel: a persistent grid of G workgroups; workgroup b takes
+//     text tiles b, b + G, ... Per tile it stages the bytes of the tile's
+//     window starts plus an (m-1)-byte halo from HBM into LDS with 16-byte
+//     loads (the next tile's loads are in flight while the current tile is
+//     searched), runs the searching loop in every lane against F and x held
+//     in LDS for the whole launch, marks candidate windows in an LDS bitmap,
+//     compares them with x, and stores the tile's count and occurrences
+//     (tile-relative starts, or the bitmap when there are many).
+//  2. hc_emit_kernel: writes every tile's occurrences as ascending int64
+//     positions at the offset given by the counts of the tiles before it.
+// No workgroup ever waits for another, so any grid size is safe.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +24,9 @@
 
 namespace hc {
 
+// Positions a tile keeps in its slot; denser tiles store their bitmap.
+constexpr uint32_t kSlot = 32;
+
 struct SearchArgs {
     const uint8_t *y;
     uint64_t n;
@@ -25,16 +34,16 @@ struct SearchArgs {
     const void *F;
     uint32_t m, q, s, mask, hv;
     uint32_t table_bytes;
-    uint32_t tile;       // window starts per tile (256 * segment)
+    uint32_t tile;       // window starts per tile (256 * segment, <= 65536)
     uint32_t seg;        // window starts per lane
     uint64_t starts;     // n - m + 1
     uint32_t n_tiles;
-    uint32_t status_cap;
     int64_t *out;
     int64_t cap;
     int64_t *d_count;
-    uint64_t *status;
-    Ctl *ctl;
+    uint32_t *counts;    // per tile: occurrences
+    uint16_t *slots;     // per tile: up to kSlot tile-relative starts
+    uint32_t *spill;     // per tile: the occurrence bitmap, when denser
 };
 
 template <int Q, typename WT, int SCHED>
@@ -43,81 +52,187 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     const LdsLayout L = lds_layout(A.tile, A.m, A.table_bytes, 0);
     uint8_t *t8 = lds + L.text_off;
     const uint32_t *t32 = reinterpret_cast<const uint32_t *>(t8);
-    uint32_t *bitmap = reinterpret_cast<uint32_t *>(lds + L.bitmap_off);
+    uint32_t *bm = reinterpret_cast<uint32_t *>(lds + L.bitmap_off);
     WT *F = reinterpret_cast<WT *>(lds + L.table_off);
     uint8_t *x8 = lds + L.x_off;
+    const uint32_t *x32 = reinterpret_cast<const uint32_t *>(x8);
     uint32_t *misc = reinterpret_cast<uint32_t *>(lds + L.misc_off);
-    // misc[0..3] wavefront sums, [4] next ticket, [5] generation, [6] tile offset, [7] flag
+    // misc: [0..3] scan, [8..9] candidate flags by tile parity
 
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const uint32_t G = gridDim.x;
+    const uint32_t tile_words = A.tile / 32u;
 
-    // F and x stay in LDS for the whole launch
+    // F and x stay in LDS for the whole launch; the bitmap starts cleared
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.F);
         uint4 *dst = reinterpret_cast<uint4 *>(F);
         for (uint32_t i = tid; i < (A.table_bytes + 15u) / 16u; i += kBlock) dst[i] = src[i];
-        for (uint32_t i = tid; i < A.m; i += kBlock) x8[i] = A.x[i];
+        for (uint32_t i = tid; i < L.x_bytes; i += kBlock) x8[i] = i < A.m ? A.x[i] : 0;
+        for (uint32_t i = tid; i < tile_words; i += kBlock) bm[i] = 0u;
     }
-    if (tid == 0) {
-        misc[5] = __hip_atomic_load(&A.ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        misc[4] = __hip_atomic_fetch_add(&A.ctl->ticket, 1u, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-        if (blockIdx.x == 0 && A.n_tiles == 0) *A.d_count = 0;
-    }
-    __syncthreads();
-    const uint32_t gen = misc[5];
-    uint32_t t = misc[4];
     const PatternView P{A.m, uint32_t(Q), A.s, A.mask, A.hv};
 
-    while (t < A.n_tiles) {
+    // ---- search phase: workgroup b takes tiles b, b + G, b + 2G, ...
+    Stage stage;
+    uint32_t tb = 0;
+    if (blockIdx.x < A.n_tiles) {
+        const uint64_t lo = uint64_t(blockIdx.x) * A.tile;
+        const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - lo));
+        tb = stage_issue(A.y, lo, lo + S + A.m - 1u, stage);
+    }
+    if (tid == 0) misc[8] = 0u;   // candidate flags, one per tile parity
+    __syncthreads();
+    uint32_t it = 0;
+    for (uint32_t t = blockIdx.x; t < A.n_tiles; t += G, ++it) {
         const uint64_t tile_lo = uint64_t(t) * A.tile;
         const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
-        const uint32_t tb = stage_text(A.y, tile_lo, tile_lo + S + A.m - 1u, t8);
-        for (uint32_t i = tid; i < A.tile / 32u; i += kBlock) bitmap[i] = 0u;
-        if (tid == 0)
-            misc[4] = __hip_atomic_fetch_add(&A.ctl->ticket, 1u, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
+        stage_commit(stage, t8);
+        lds_barrier();
 
+        // the next tile's bytes travel while this one is searched
+        const uint32_t tb_cur = tb;
+        if (t + G < A.n_tiles) {
+            const uint64_t lo = uint64_t(t + G) * A.tile;
+            const uint32_t Sn = uint32_t(min<uint64_t>(A.tile, A.starts - lo));
+            tb = stage_issue(A.y, lo, lo + Sn + A.m - 1u, stage);
+        }
         if constexpr (SCHED == HC_SCHED_WAVE) {
             const uint32_t per = (S + 3u) / 4u;
             const uint32_t lo = min(S, wid * per), hi = min(S, lo + per);
-            hc_wave<Q, WT>(t32, t8, tb, F, x8, P, lo, hi, bitmap, lane);
+            hc_wave<Q, WT>(t32, tb_cur, F, P, lo, hi, bm, lane, &misc[8 + (it & 1u)]);
         } else {
             const uint32_t lo = min(S, tid * A.seg), hi = min(S, lo + A.seg);
-            if (lo < hi) hc_segment<Q, WT>(t32, t8, tb, F, x8, P, lo + A.m - 1u, hi + A.m - 1u, bitmap);
+            if (lo < hi)
+                hc_segment<Q, WT>(t32, tb_cur, F, P, lo + A.m - 1u, hi + A.m - 1u, bm,
+                                  &misc[8 + (it & 1u)]);
         }
-        __syncthreads();
+        lds_barrier();
 
-        // ordered compaction of the tile's bitmap
+        // most tiles hold no candidate at all: then nothing to compare or write
+        if (misc[8 + (it & 1u)] == 0u) {
+            if (tid == 0) {
+                A.counts[t] = 0u;
+                misc[8 + ((it + 1u) & 1u)] = 0u;   // flag of the next tile
+            }
+            continue;
+        }
+        if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;
+
+        // compare candidates with x; count this thread's share of the tile
         const uint32_t words = (S + 31u) / 32u;
         const uint32_t wpt = (words + kBlock - 1u) / kBlock;
         const uint32_t w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
         uint32_t c = 0;
-        for (uint32_t i = w0; i < w1; ++i) c += __popc(bitmap[i]);
-        uint32_t total;
-        const uint32_t mine = block_exclusive_scan(c, misc, &total);
-        if (wid == 0) {
-            const uint32_t excl = lookback(A.status, t, gen, total, lane, &A.ctl->err);
-            if (lane == 0) {
-                misc[6] = excl;
-                if (t == A.n_tiles - 1u) *A.d_count = int64_t(excl) + total;
-            }
-        }
-        __syncthreads();
-        int64_t idx = int64_t(misc[6]) + mine;
-        for (uint32_t i = w0; i < w1 && idx < A.cap; ++i) {
-            uint32_t b = bitmap[i];
-            while (b && idx < A.cap) {
+        for (uint32_t i = w0; i < w1; ++i) {
+            uint32_t b = bm[i], keep = b;
+            while (b) {
                 const uint32_t bit = __builtin_ctz(b);
                 b &= b - 1u;
-                A.out[idx++] = int64_t(tile_lo + i * 32u + bit);
+                if (!window_equals(t32, tb_cur + i * 32u + bit, x32, A.m)) keep &= ~(1u << bit);
+            }
+            bm[i] = keep;
+            c += __popc(keep);
+        }
+        uint32_t total;
+        const uint32_t mine = block_exclusive_scan(c, misc, &total);
+        if (tid == 0) A.counts[t] = total;
+        if (total != 0u) {
+            if (total <= kSlot) {
+                uint32_t j = mine;
+                for (uint32_t i = w0; i < w1; ++i) {
+                    uint32_t b = bm[i];
+                    while (b) {
+                        const uint32_t bit = __builtin_ctz(b);
+                        b &= b - 1u;
+                        A.slots[uint64_t(t) * kSlot + j++] = uint16_t(i * 32u + bit);
+                    }
+                }
+            } else {
+                for (uint32_t i = w0; i < w1; ++i) A.spill[uint64_t(t) * tile_words + i] = bm[i];
+            }
+            for (uint32_t i = w0; i < w1; ++i) bm[i] = 0u;
+        }
+    }
+
+}
+
+// Ordered output: workgroup b writes the occurrences of tiles
+// [b * per, (b + 1) * per) in tile order. Its offset is the sum of the counts
+// of all earlier tiles, read in parallel; the search kernel has finished, so
+// every count, slot and spilled bitmap is visible.
+struct EmitArgs {
+    uint32_t n_tiles, tile, per;
+    uint64_t starts;
+    const uint32_t *counts;
+    const uint16_t *slots;
+    const uint32_t *spill;
+    int64_t *out;
+    int64_t cap;
+    int64_t *d_count;
+};
+
+__global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
+    __shared__ uint32_t lds_w[4];
+    __shared__ uint32_t cnt[kBlock];
+    __shared__ uint32_t off[kBlock];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile_words = A.tile / 32u;
+    if (A.n_tiles == 0) {
+        if (blockIdx.x == 0 && tid == 0) *A.d_count = 0;
+        return;
+    }
+    const uint32_t r0 = min(A.n_tiles, blockIdx.x * A.per), r1 = min(A.n_tiles, r0 + A.per);
+    if (r0 >= r1) return;
+    uint32_t part = 0;
+    for (uint32_t i = tid; i < r0; i += kBlock) part += A.counts[i];
+    uint32_t before;
+    (void)block_exclusive_scan(part, lds_w, &before);
+    lds_barrier();
+    int64_t prefix = before;
+    // this workgroup's tiles, up to 256 at a time
+    for (uint32_t c0 = r0; c0 < r1; c0 += kBlock) {
+        const uint32_t nc = min(kBlock, r1 - c0);
+        const uint32_t mycnt = tid < nc ? A.counts[c0 + tid] : 0u;
+        uint32_t chunk_total;
+        const uint32_t myoff = block_exclusive_scan(mycnt, lds_w, &chunk_total);
+        cnt[tid] = mycnt;
+        off[tid] = myoff;
+        lds_barrier();
+        for (uint32_t j = 0; j < nc; ++j) {
+            const uint32_t c = cnt[j];
+            if (c == 0u) continue;
+            const uint32_t t = c0 + j;
+            const uint64_t tile_lo = uint64_t(t) * A.tile;
+            const int64_t base = prefix + off[j];
+            if (c <= kSlot) {
+                if (tid < c && base + tid < A.cap)
+                    A.out[base + tid] = int64_t(tile_lo + A.slots[uint64_t(t) * kSlot + tid]);
+            } else {
+                const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
+                const uint32_t words = (S + 31u) / 32u;
+                const uint32_t wpt = (words + kBlock - 1u) / kBlock;
+                const uint32_t w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
+                const uint32_t *sb = A.spill + uint64_t(t) * tile_words;
+                uint32_t k = 0;
+                for (uint32_t i = w0; i < w1; ++i) k += __popc(sb[i]);
+                uint32_t tot;
+                int64_t idx = base + block_exclusive_scan(k, lds_w, &tot);
+                lds_barrier();
+                for (uint32_t i = w0; i < w1 && idx < A.cap; ++i) {
+                    uint32_t b = sb[i];
+                    while (b && idx < A.cap) {
+                        const uint32_t bit = __builtin_ctz(b);
+                        b &= b - 1u;
+                        A.out[idx++] = int64_t(tile_lo + i * 32u + bit);
+                    }
+                }
             }
         }
-        t = misc[4];
-        __syncthreads();
+        prefix += chunk_total;
+        lds_barrier();
     }
-    finish_launch(A.ctl, A.status, A.status_cap, gen, &misc[7], A.d_count);
+    if (r1 == A.n_tiles && tid == 0) *A.d_count = prefix;
 }
 
 // ----------------------------------------------------------------------------
@@ -180,20 +295,22 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     const uint32_t table_bytes = uint32_t(pd.F.size() * (pd.w / 8));
     const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
 
-    uint32_t seg = uint32_t(lc.segment);
+    uint32_t seg = std::min<uint32_t>(uint32_t(lc.segment), 256u);   // tile-relative starts fit 16 bits
     LdsLayout L = lds_layout(kBlock * seg, m, table_bytes, 0);
     while (L.total > di.max_lds_per_block && seg > 8) {
         seg = std::max<uint32_t>(8, seg / 2);
         L = lds_layout(kBlock * seg, m, table_bytes, 0);
     }
-    if (L.total > di.max_lds_per_block) return HC_EINVAL;
+    while (kBlock * seg + m - 1u > stage_limit(kBlock) && seg > 8) seg -= 4;
+    if (L.total > di.max_lds_per_block || kBlock * seg + m - 1u > stage_limit(kBlock)) return HC_EINVAL;
+    L = lds_layout(kBlock * seg, m, table_bytes, 0);
     const uint32_t tile = kBlock * seg;
     const uint64_t n_tiles64 = (starts + tile - 1) / tile;
     if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
     const uint32_t n_tiles = uint32_t(n_tiles64);
 
     Workspace *ws = nullptr;
-    hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), &ws);
+    hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
     if (st != HC_OK) return st;
 
     KernelFn fn = pick_kernel(pd.q, pd.w, lc.schedule);
@@ -216,13 +333,28 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     A.seg = seg;
     A.starts = starts;
     A.n_tiles = n_tiles;
-    A.status_cap = ws->status_cap;
     A.out = d_out;
     A.cap = cap;
     A.d_count = d_count;
-    A.status = ws->status;
-    A.ctl = reinterpret_cast<Ctl *>(ws->ctl);
+    A.counts = ws->counts;
+    A.slots = ws->slots;
+    A.spill = ws->spill;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
+    if (hipGetLastError() != hipSuccess) return HC_EHIP;
+
+    EmitArgs E;
+    E.n_tiles = n_tiles;
+    E.tile = tile;
+    const uint32_t emit_grid = std::max<uint32_t>(1, std::min<uint32_t>(n_tiles, uint32_t(di.cus) * 2u));
+    E.per = (n_tiles + emit_grid - 1) / emit_grid;
+    E.starts = starts;
+    E.counts = ws->counts;
+    E.slots = ws->slots;
+    E.spill = ws->spill;
+    E.out = d_out;
+    E.cap = cap;
+    E.d_count = d_count;
+    hipLaunchKernelGGL(hc_emit_kernel, dim3(emit_grid), dim3(kBlock), 0, stream, E);
     return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
 }
 

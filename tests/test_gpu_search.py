@@ -210,6 +210,8 @@ def test_repeated_launches_and_streams(torch_dev):
         out = torch.empty(n, dtype=torch.int64, device=torch_dev)
         cnt = torch.zeros(1, dtype=torch.int64, device=torch_dev)
         announce("repeat", i, n)
+        if s is not None:   # the buffers above were filled on the current stream
+            s.wait_stream(torch.cuda.current_stream())
         B.hc_search_async(p, yd[:n], out, cnt, launch=(int(rs.choice([8, 36, 132])), 1, 0, 0),
                           stream=s)
         outs.append((n, out, cnt))
