@@ -34,6 +34,7 @@ struct LdsLayout {
     uint32_t bitmap_off, bitmap_bytes;
     uint32_t table_off, table_bytes;
     uint32_t x_off, x_bytes;
+    uint32_t park_off, park_bytes;
     uint32_t misc_off, misc_bytes;
     uint32_t total;
 };
@@ -56,7 +57,9 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t tile, uint32_t m, uint3
     L.table_bytes = align16(table_bytes);
     L.x_off = L.table_off + L.table_bytes;
     L.x_bytes = align16(m) + 32u;
-    L.misc_off = L.x_off + L.x_bytes;
+    L.park_off = L.x_off + L.x_bytes;
+    L.park_bytes = 32u * 24u;   // parked chain walks
+    L.misc_off = L.park_off + L.park_bytes;
     L.misc_bytes = 128u;
     L.total = L.misc_off + L.misc_bytes;
     return L;
@@ -137,28 +140,44 @@ struct PatternView {
     uint32_t m, q, s, mask, hv;
 };
 
-// One attempt of the searching phase at window end J (LDS byte position of
-// the window's last character is tb + J), given the hash v of the q-gram that
-// ends at J and its word z = F[v] != 0. Follows the chain of q-grams ending
-// at J - q, J - 2q, ... while they stay inside the window; each must carry
-// its link bit in the word of the q-gram after it. Returns the next window
-// end. When every q-gram links and the last hash equals H_v, *hit is set: the
-// window is a candidate, compared with x in a later pass.
+// A chain walk that a lane has parked for its wavefront to finish: window end
+// J, the end e of the last q-gram checked so far, its hash v and its word z.
+struct Parked {
+    uint32_t J, e, v, owner;   // owner: thread id * 2 + stream
+    uint64_t z;
+};
+constexpr uint32_t kParkCap = 32;   // parked walks per workgroup and round
+constexpr int kLocalSteps = 8;      // chain steps a lane takes before parking
+
+// Outcome of an attempt: the next window end, or "parked".
+constexpr uint32_t kParkedJ = 0xFFFFFFFFu;
+
+// Chain walk of the searching phase for the window ending at J, from the
+// q-gram ending at e (hash v, word z = F[v] != 0) towards the window start:
+// the q-grams ending at e - q, e - 2q, ... are hashed while they stay inside
+// the window; each must carry its link bit in the word of the q-gram after
+// it. A broken link at the q-gram ending at e' moves the window end to
+// e' + m - q + 1 (u_p u is not a factor of x). When every q-gram links and the
+// last hash equals H_v the window is a candidate (*hit), compared with x in a
+// later pass, and the window end moves by one. After `steps` links the walk is
+// handed back (kParkedJ) with its position in (e, v, z).
 template <int Q, typename WT>
 __device__ __forceinline__ uint32_t hc_chain(const uint32_t *__restrict__ t32, uint32_t tb,
                                              const WT *__restrict__ F, const PatternView &P,
-                                             uint32_t J, uint32_t v, WT z, bool *hit) {
+                                             uint32_t J, uint32_t &e, uint32_t &v, WT &z,
+                                             int steps, bool *hit) {
     const uint32_t shift = P.m - Q + 1u;
-    int32_t e = int32_t(J);
     const int32_t lo = int32_t(J) - int32_t(P.m) + 2 * Q;
-    while (e >= lo) {                        // a whole q-gram still fits before e
-        e -= Q;
-        v = qgram_hash<Q>(t32, tb + uint32_t(e), P.s, P.mask);
-        if (!linked(z, v)) return uint32_t(e) + shift;   // u_p u is not a factor
-        z = F[v];
+    while (int32_t(e) >= lo) {               // a whole q-gram still fits before e
+        if (steps-- == 0) return kParkedJ;
+        const uint32_t ep = e - Q;
+        const uint32_t vp = qgram_hash<Q>(t32, tb + ep, P.s, P.mask);
+        if (!linked(z, vp)) return ep + shift;
+        e = ep;
+        v = vp;
+        z = F[vp];
     }
-    // every q-gram of the window is linked: candidate
-    if (v == P.hv) *hit = true;
+    if (v == P.hv) *hit = true;              // every q-gram of the window links
     return J + 1u;
 }
 
@@ -166,10 +185,11 @@ template <int Q, typename WT>
 __device__ __forceinline__ uint32_t hc_attempt(const uint32_t *__restrict__ t32, uint32_t tb,
                                                const WT *__restrict__ F, const PatternView &P,
                                                uint32_t J, bool *hit) {
-    const uint32_t v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
-    const WT z = F[v];
+    uint32_t v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
+    WT z = F[v];
     if (z == 0) return J + P.m - Q + 1u;     // no q-gram of x hashes here
-    return hc_chain<Q, WT>(t32, tb, F, P, J, v, z, hit);
+    uint32_t e = J;
+    return hc_chain<Q, WT>(t32, tb, F, P, J, e, v, z, 1 << 30, hit);
 }
 
 __device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t st, uint32_t *any) {
@@ -177,44 +197,120 @@ __device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t st, uint32_t *an
     *any = 1u;
 }
 
-// Searching loop over window ends [jlo, jhi) (tile-relative), one lane.
-// The range is split in two halves searched side by side, so that the LDS
-// round trips of two independent attempts overlap. Marks the start of each
-// candidate window in the tile bitmap and sets *any.
+// Searching loop of one lane over window ends [J0, jmid) and [J1, jhi)
+// (tile-relative), the two halves of its range searched side by side so that
+// the LDS round trips of two independent attempts overlap. Marks candidate
+// window starts in the tile bitmap and sets *any. A chain walk longer than
+// kLocalSteps is parked in `park` (capacity kParkCap, count *npark) and the
+// lane stops; it resumes after its wavefront has finished the walk. Returns
+// false when the lane parked a walk.
 template <int Q, typename WT>
-__device__ __forceinline__ void hc_segment(const uint32_t *__restrict__ t32, uint32_t tb,
+__device__ __forceinline__ bool hc_segment(const uint32_t *__restrict__ t32, uint32_t tb,
                                            const WT *__restrict__ F, const PatternView &P,
-                                           uint32_t jlo, uint32_t jhi, uint32_t *bitmap,
-                                           uint32_t *any) {
+                                           uint32_t &J0, uint32_t jmid, uint32_t &J1, uint32_t jhi,
+                                           uint32_t *bitmap, uint32_t *any, Parked *park,
+                                           uint32_t *npark, uint32_t *myslot) {
     const uint32_t shift = P.m - Q + 1u;
-    const uint32_t jmid = jlo + ((jhi - jlo) >> 1);
-    uint32_t J0 = jlo, J1 = jmid;
+    const uint32_t jany = J0 < jmid ? J0 : (J1 < jhi ? J1 : 0u);
     while (J0 < jmid || J1 < jhi) {
-        // a finished half re-reads its first window (in the tile), unused
-        const uint32_t a0 = J0 < jmid ? J0 : jlo, a1 = J1 < jhi ? J1 : jlo;
-        const uint32_t v0 = qgram_hash<Q>(t32, tb + a0, P.s, P.mask);
-        const uint32_t v1 = qgram_hash<Q>(t32, tb + a1, P.s, P.mask);
-        const WT z0 = F[v0], z1 = F[v1];
-        if (J0 < jmid) {
-            if (z0 == 0) {
-                J0 += shift;                     // empty word: shift by m - q + 1
-            } else {
-                bool hit = false;
-                const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J0, v0, z0, &hit);
-                if (hit) mark(bitmap, J0 + 1u - P.m, any);
-                J0 = next;
+        // a finished half re-reads a window of this lane (in the tile), unused
+        const uint32_t a0 = J0 < jmid ? J0 : jany, a1 = J1 < jhi ? J1 : jany;
+        uint32_t v0 = qgram_hash<Q>(t32, tb + a0, P.s, P.mask);
+        uint32_t v1 = qgram_hash<Q>(t32, tb + a1, P.s, P.mask);
+        WT z0 = F[v0], z1 = F[v1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t &J = h == 0 ? J0 : J1;
+            const uint32_t Jend = h == 0 ? jmid : jhi;
+            uint32_t v = h == 0 ? v0 : v1;
+            WT z = h == 0 ? z0 : z1;
+            if (J >= Jend) continue;
+            if (z == 0) {
+                J += shift;                      // empty word: shift by m - q + 1
+                continue;
             }
-        }
-        if (J1 < jhi) {
-            if (z1 == 0) {
-                J1 += shift;
-            } else {
-                bool hit = false;
-                const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J1, v1, z1, &hit);
-                if (hit) mark(bitmap, J1 + 1u - P.m, any);
-                J1 = next;
+            bool hit = false;
+            uint32_t e = J;
+            const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J, e, v, z, kLocalSteps, &hit);
+            if (next == kParkedJ) {
+                const uint32_t slot = atomicAdd(npark, 1u);
+                if (slot < kParkCap) {
+                    park[slot] = Parked{J, e, v, threadIdx.x * 2u + uint32_t(h), uint64_t(z)};
+                    *myslot = slot;
+                    return false;
+                }
+                // no room: finish the walk here
+                const uint32_t n2 = hc_chain<Q, WT>(t32, tb, F, P, J, e, v, z, 1 << 30, &hit);
+                if (hit) mark(bitmap, J + 1u - P.m, any);
+                J = n2;
+                continue;
             }
+            if (hit) mark(bitmap, J + 1u - P.m, any);
+            J = next;
         }
+    }
+    return true;
+}
+
+// A whole wavefront finishes a parked chain walk: lane i hashes the q-gram
+// that ends i + 1 steps further back and looks up its word, so 64 links are
+// checked per round; a ballot finds the first broken one. Returns the next
+// window end of the walk's window and marks it when it is a candidate.
+template <int Q, typename WT>
+__device__ __forceinline__ uint32_t hc_chain_wave(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                  const WT *__restrict__ F, const PatternView &P,
+                                                  const Parked &pk, uint32_t lane,
+                                                  uint32_t *bitmap, uint32_t *any) {
+    const uint32_t shift = P.m - Q + 1u;
+    const int32_t lo = int32_t(pk.J) - int32_t(P.m) + 2 * Q;
+    int32_t e = int32_t(pk.e);
+    WT z = WT(pk.z);
+    uint32_t v = pk.v;
+    while (true) {
+        // step i (1-based) checks the q-gram ending at e - i q; it exists when
+        // the previous end e - (i - 1) q is still >= lo
+        const int32_t step = int32_t(lane) + 1;
+        const int32_t ei = e - step * Q;
+        const bool valid = e - (step - 1) * Q >= lo;
+        uint32_t vi = 0;
+        WT zi = 0;
+        if (valid) {
+            vi = qgram_hash<Q>(t32, tb + uint32_t(ei), P.s, P.mask);
+            zi = F[vi];
+        }
+        // word of the q-gram after step i: step i - 1's word, or z for step 1
+        WT zprev;
+        if constexpr (sizeof(WT) == 8) {
+            const uint32_t lo32 = (uint32_t)__shfl_up((int)uint32_t(zi), 1, kWave);
+            const uint32_t hi32 = (uint32_t)__shfl_up((int)uint32_t(uint64_t(zi) >> 32), 1, kWave);
+            zprev = WT((uint64_t(hi32) << 32) | lo32);
+        } else {
+            zprev = WT((uint32_t)__shfl_up((int)uint32_t(zi), 1, kWave));
+        }
+        if (lane == 0) zprev = z;
+        const uint64_t broken = __ballot(valid && !linked(zprev, vi));
+        if (broken) {
+            const int f = __ffsll((unsigned long long)broken) - 1;
+            return uint32_t(e - (f + 1) * Q) + shift;
+        }
+        const uint64_t vmask = __ballot(valid);
+        if (vmask != ~0ull) {
+            // the walk reached the window start inside this round
+            const int last = vmask ? 63 - __clzll((long long)vmask) : -1;
+            const uint32_t vl = last >= 0 ? (uint32_t)__shfl((int)vi, last, kWave) : v;
+            if (vl == P.hv && lane == 0) mark(bitmap, pk.J + 1u - P.m, any);
+            return pk.J + 1u;
+        }
+        // all 64 steps linked: continue from the last one
+        v = (uint32_t)__shfl((int)vi, 63, kWave);
+        if constexpr (sizeof(WT) == 8) {
+            const uint32_t lo32 = (uint32_t)__shfl((int)uint32_t(zi), 63, kWave);
+            const uint32_t hi32 = (uint32_t)__shfl((int)uint32_t(uint64_t(zi) >> 32), 63, kWave);
+            z = WT((uint64_t(hi32) << 32) | lo32);
+        } else {
+            z = WT((uint32_t)__shfl((int)uint32_t(zi), 63, kWave));
+        }
+        e -= 64 * Q;
     }
 }
 

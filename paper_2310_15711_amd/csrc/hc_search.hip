@@ -56,8 +56,10 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     WT *F = reinterpret_cast<WT *>(lds + L.table_off);
     uint8_t *x8 = lds + L.x_off;
     const uint32_t *x32 = reinterpret_cast<const uint32_t *>(x8);
+    Parked *park = reinterpret_cast<Parked *>(lds + L.park_off);
     uint32_t *misc = reinterpret_cast<uint32_t *>(lds + L.misc_off);
-    // misc: [0..3] scan, [8..9] candidate flags by tile parity
+    // misc: [0..3] scan, [8..9] candidate flags by tile parity, [10..11]
+    // parked-walk counts by round parity
 
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const uint32_t G = gridDim.x;
@@ -81,8 +83,13 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
         const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - lo));
         tb = stage_issue(A.y, lo, lo + S + A.m - 1u, stage);
     }
-    if (tid == 0) misc[8] = 0u;   // candidate flags, one per tile parity
+    if (tid == 0) {
+        misc[8] = 0u;    // candidate flags, one per tile parity
+        misc[10] = 0u;   // parked-walk counts, one per round parity
+        misc[11] = 0u;
+    }
     __syncthreads();
+    uint32_t round = 0;
     uint32_t it = 0;
     for (uint32_t t = blockIdx.x; t < A.n_tiles; t += G, ++it) {
         const uint64_t tile_lo = uint64_t(t) * A.tile;
@@ -97,17 +104,45 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
             const uint32_t Sn = uint32_t(min<uint64_t>(A.tile, A.starts - lo));
             tb = stage_issue(A.y, lo, lo + Sn + A.m - 1u, stage);
         }
+        uint32_t *any = &misc[8 + (it & 1u)];
         if constexpr (SCHED == HC_SCHED_WAVE) {
             const uint32_t per = (S + 3u) / 4u;
             const uint32_t lo = min(S, wid * per), hi = min(S, lo + per);
-            hc_wave<Q, WT>(t32, tb_cur, F, P, lo, hi, bm, lane, &misc[8 + (it & 1u)]);
+            hc_wave<Q, WT>(t32, tb_cur, F, P, lo, hi, bm, lane, any);
+            lds_barrier();
         } else {
+            // the lane's window ends, in two halves searched side by side
             const uint32_t lo = min(S, tid * A.seg), hi = min(S, lo + A.seg);
-            if (lo < hi)
-                hc_segment<Q, WT>(t32, tb_cur, F, P, lo + A.m - 1u, hi + A.m - 1u, bm,
-                                  &misc[8 + (it & 1u)]);
+            const uint32_t jlo = lo + A.m - 1u, jhi = hi + A.m - 1u;
+            const uint32_t jmid = jlo + ((jhi - jlo) >> 1);
+            uint32_t J0 = jlo, J1 = jmid, myslot = kParkCap;
+            bool running = lo < hi;
+            while (true) {
+                uint32_t *npark = &misc[10 + (round & 1u)];
+                if (running) {
+                    running = !hc_segment<Q, WT>(t32, tb_cur, F, P, J0, jmid, J1, jhi, bm, any, park,
+                                                 npark, &myslot);
+                    // `running` now means: parked, resumes after the walk is finished
+                }
+                lds_barrier();
+                const uint32_t np = min(*npark, kParkCap);
+                if (tid == 0) misc[10 + ((round + 1u) & 1u)] = 0u;
+                ++round;
+                if (np == 0u) break;
+                // long chain walks, finished by whole wavefronts
+                for (uint32_t i = wid; i < np; i += kBlock / kWave) {
+                    const Parked pk = park[i];
+                    const uint32_t next = hc_chain_wave<Q, WT>(t32, tb_cur, F, P, pk, lane, bm, any);
+                    if (lane == 0) park[i].J = next;
+                }
+                lds_barrier();
+                if (running) {
+                    const Parked &pk = park[myslot];
+                    if ((pk.owner & 1u) == 0u) J0 = pk.J; else J1 = pk.J;
+                    myslot = kParkCap;
+                }
+            }
         }
-        lds_barrier();
 
         // most tiles hold no candidate at all: then nothing to compare or write
         if (misc[8 + (it & 1u)] == 0u) {
