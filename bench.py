@@ -54,11 +54,132 @@ def parse():
                     help="oracle sample: patterns per (sigma, m)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--detail", action="store_true", help="print per-(sigma, m) figures to stderr")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--summarize", nargs=4, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "CALIB_PREFIX"),
+                    help="turn rocprofv3 outputs into profiles/ summaries and traffic.json")
+    ap.add_argument("--summary-cmd", default="", help="command lines quoted in the summary")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """Hash of the search kernel's sources: traffic figures taken with other
+    sources are not reported."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("hc_search.hip", "hc_device.h"):
+        with open(os.path.join(ROOT, "paper_2310_15711_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def calib_copy():
+    """A plain device copy of 256 MiB (reads 256 MiB, writes 256 MiB): the
+    FETCH_SIZE / WRITE_SIZE it reports give the scale of those counters."""
+    import torch
+
+    n = 256 << 20
+    # four sources, copied in rotation: 1 GiB does not fit the 256 MB
+    # last-level cache, so each copy reads its source from HBM
+    srcs = [torch.empty(n, dtype=torch.uint8, device="cuda").fill_(i) for i in range(4)]
+    b = torch.empty_like(srcs[0])
+    torch.cuda.synchronize()
+    for i in range(8):
+        b.copy_(srcs[i % 4])
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": n, "copies": 8}), flush=True)
+
+
+def _read_csv(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _find(d, suffix):
+    for root, _, files in os.walk(d):
+        for fn in files:
+            if fn.endswith(suffix):
+                return os.path.join(root, fn)
+    raise FileNotFoundError(f"{suffix} under {d}")
+
+
+def _counter_per_dispatch(d, counter, name_part):
+    """Mean of a counter over the dispatches of kernels whose name contains
+    name_part, summed per dispatch (rocprofv3 lists one row per dispatch)."""
+    rows = _read_csv(_find(d, "counter_collection.csv"))
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return (sum(per.values()) / len(per)) if per else None, len(per)
+
+
+def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
+    stats = _read_csv(_find(stats_dir, "kernel_stats.csv"))
+    lines = ["# rocprofv3 kernel statistics: single-pattern HC search, sigma in {4,20,64}, "
+             "m in {2..1024}, 256 MiB texts", "", "Command(s):", "", "```", cmd.strip(), "```", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    avg = {}
+    for r in stats:
+        name = r["Name"]
+        short = name.split("(")[0].replace("void ", "")[:90]
+        a = float(r["AverageNs"]) / 1e3
+        avg[short] = (int(r["Calls"]), a)
+        lines.append(f"| `{short}` | {r['Calls']} | {a:.2f} | {float(r['MinNs'])/1e3:.2f} | "
+                     f"{float(r['MaxNs'])/1e3:.2f} | {float(r['Percentage']):.2f}% |")
+    search = [v for k, v in avg.items() if "hc_search_kernel" in k]
+    emit = [v for k, v in avg.items() if "hc_emit_kernel" in k]
+    if search and emit:
+        calls = sum(c for c, _ in search)
+        s_avg = sum(c * a for c, a in search) / calls
+        e_avg = sum(c * a for c, a in emit) / sum(c for c, _ in emit)
+        lines += ["", f"Search call = `hc_search_kernel` + `hc_emit_kernel`: average {s_avg:.2f} + "
+                      f"{e_avg:.2f} = {s_avg + e_avg:.2f} us per call ({calls} calls)."]
+    out = os.path.join(ROOT, "profiles", "hc_search_single_pattern_kernel_stats.md")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    # traffic: HBM bytes per search call, scaled by the copy kernel's counters
+    fetch_s, nf = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "hc_search_kernel")
+    fetch_e, _ = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "hc_emit_kernel")
+    write_s, nw = _counter_per_dispatch(write_dir, "WRITE_SIZE", "hc_search_kernel")
+    write_e, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", "hc_emit_kernel")
+    cf, _ = _counter_per_dispatch(calib_prefix + "_fetch", "FETCH_SIZE", "")
+    cw, _ = _counter_per_dispatch(calib_prefix + "_write", "WRITE_SIZE", "")
+    copy_bytes = 256 << 20
+    kf = copy_bytes / (cf * 1024.0)    # bytes per counted KiB
+    kw = copy_bytes / (cw * 1024.0)
+    fetch = ((fetch_s or 0) + (fetch_e or 0)) * 1024.0 * kf
+    write = ((write_s or 0) + (write_e or 0)) * 1024.0 * kw
+    tj = {"workload": "single", "kernel_source": kernel_source_hash(),
+          "bytes_per_launch": round(fetch + write),
+          "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+          "dispatches": nf, "copy_fetch_kib": cf, "copy_write_kib": cw,
+          "fetch_scale": kf, "write_scale": kw}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(tj, f, indent=1)
+    lines = ["# HBM traffic of the single-pattern search call (rocprofv3 --pmc)", "",
+             "Command(s):", "", "```", cmd.strip(), "```", "",
+             f"- FETCH_SIZE per call (search + emit kernels): {(fetch_s or 0) + (fetch_e or 0):.0f} KiB "
+             f"over {nf} calls; WRITE_SIZE per call: {(write_s or 0) + (write_e or 0):.0f} KiB.",
+             f"- Calibration: a plain 256 MiB device copy reads FETCH_SIZE = {cf:.0f} KiB and "
+             f"WRITE_SIZE = {cw:.0f} KiB (ideal 262144 KiB each); scale factors {kf:.4f} and {kw:.4f}.",
+             f"- Scaled HBM bytes per call: fetch {fetch/1e6:.1f} MB + write {write/1e6:.1f} MB = "
+             f"{(fetch + write)/1e6:.1f} MB.", ""]
+    with open(os.path.join(ROOT, "profiles", "hc_search_single_pattern_traffic.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(tj))
 
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize(*args.summarize, args.summary_cmd)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -70,6 +191,9 @@ def main():
     from paper_2310_15711_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.calib_copy:
+        calib_copy()
+        return
     dev = torch.device("cuda:0")
     B.lib()
     n = args.text_mib << 20
@@ -163,7 +287,7 @@ def main():
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == args.workload:
+            if tj.get("workload") == args.workload and tj.get("kernel_source") == kernel_source_hash():
                 traffic = tj.get("bytes_per_launch")
         except Exception:
             traffic = None

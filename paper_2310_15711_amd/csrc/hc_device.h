@@ -198,37 +198,61 @@ __device__ __forceinline__ void mark(uint32_t *bitmap, uint32_t st, uint32_t *an
 }
 
 // Searching loop of one lane over window ends [J0, jmid) and [J1, jhi)
-// (tile-relative), the two halves of its range searched side by side so that
-// the LDS round trips of two independent attempts overlap. Marks candidate
-// window starts in the tile bitmap and sets *any. A chain walk longer than
-// kLocalSteps is parked in `park` (capacity kParkCap, count *npark) and the
-// lane stops; it resumes after its wavefront has finished the walk. Returns
-// false when the lane parked a walk.
-template <int Q, typename WT>
+// (tile-relative), the two halves of its range searched side by side. Each
+// half also looks K attempts ahead: the words of the q-grams ending at J,
+// J + s, ..., J + (K-1) s (s = m - q + 1, the shift after an empty word) are
+// fetched together, and the first non-empty one continues the search there
+// (the attempts before it would each have shifted by s). Up to 2K LDS round
+// trips are thus in flight per lane. Marks candidate window starts in the
+// tile bitmap and sets *any. A chain walk longer than kLocalSteps is parked
+// in `park` (capacity kParkCap, count *npark, slot *myslot) and the lane
+// stops; it resumes after its wavefront has finished the walk. Returns false
+// when the lane parked a walk.
+template <int Q, typename WT, int K>
 __device__ __forceinline__ bool hc_segment(const uint32_t *__restrict__ t32, uint32_t tb,
                                            const WT *__restrict__ F, const PatternView &P,
                                            uint32_t &J0, uint32_t jmid, uint32_t &J1, uint32_t jhi,
                                            uint32_t *bitmap, uint32_t *any, Parked *park,
                                            uint32_t *npark, uint32_t *myslot) {
     const uint32_t shift = P.m - Q + 1u;
-    const uint32_t jany = J0 < jmid ? J0 : (J1 < jhi ? J1 : 0u);
+    const uint32_t jsafe = J0 < jmid ? J0 : J1;   // a window end of this lane's range
     while (J0 < jmid || J1 < jhi) {
-        // a finished half re-reads a window of this lane (in the tile), unused
-        const uint32_t a0 = J0 < jmid ? J0 : jany, a1 = J1 < jhi ? J1 : jany;
-        uint32_t v0 = qgram_hash<Q>(t32, tb + a0, P.s, P.mask);
-        uint32_t v1 = qgram_hash<Q>(t32, tb + a1, P.s, P.mask);
-        WT z0 = F[v0], z1 = F[v1];
+        uint32_t vv[2][K];
+        WT zz[2][K];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t J = h == 0 ? J0 : J1, Jend = h == 0 ? jmid : jhi;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                // positions past the half's end read a window of the lane instead (unused)
+                const uint32_t Jn = J + uint32_t(i) * shift;
+                const uint32_t Ji = Jn < Jend ? Jn : jsafe;
+                vv[h][i] = qgram_hash<Q>(t32, tb + Ji, P.s, P.mask);
+                zz[h][i] = F[vv[h][i]];
+            }
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             uint32_t &J = h == 0 ? J0 : J1;
             const uint32_t Jend = h == 0 ? jmid : jhi;
-            uint32_t v = h == 0 ? v0 : v1;
-            WT z = h == 0 ? z0 : z1;
             if (J >= Jend) continue;
-            if (z == 0) {
-                J += shift;                      // empty word: shift by m - q + 1
+            int first = K;
+#pragma unroll
+            for (int i = K - 1; i >= 0; --i)
+                if (zz[h][i] != 0 && J + uint32_t(i) * shift < Jend) first = i;
+            if (first == K) {
+                J += uint32_t(K) * shift;        // K empty words in a row
                 continue;
             }
+            uint32_t v = vv[h][0];
+            WT z = zz[h][0];
+#pragma unroll
+            for (int i = 1; i < K; ++i)
+                if (first == i) {
+                    v = vv[h][i];
+                    z = zz[h][i];
+                }
+            J += uint32_t(first) * shift;
             bool hit = false;
             uint32_t e = J;
             const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J, e, v, z, kLocalSteps, &hit);

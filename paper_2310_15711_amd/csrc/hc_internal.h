@@ -34,7 +34,8 @@ struct PatternData {
 
 int alpha_max(int w);
 hc_status validate_params(int64_t m, int q, int alpha, int w);
-void default_params(int64_t m, int &q, int &alpha, int &w);
+void default_params(int64_t m, int distinct, int &q, int &alpha, int &w);
+int distinct_bytes(const uint8_t *x, int64_t m);
 
 // Builds F, s, mask and H_v (host).
 void build_link_table(const uint8_t *x, int64_t m, int q, int alpha, int w,

@@ -34,22 +34,37 @@ hc_status validate_params(int64_t m, int q, int alpha, int w) {
     return HC_OK;
 }
 
-// Built-in priors when the caller leaves a parameter at 0. Section 4 reports
-// the best variants HC(q, alpha) in the range q <= 8, 8 <= alpha <= 12: q
-// between 3 and 8 with alpha 11-12 for m >= 16, q = 3-4 for m = 8. Short
-// patterns need q <= m.
-void default_params(int64_t m, int &q, int &alpha, int &w) {
-    if (q == 0) {
-        if (m <= 2) q = 1;
-        else if (m <= 4) q = 2;
-        else if (m <= 8) q = 3;
-        else if (m <= 16) q = 4;
-        else if (m <= 256) q = 5;
-        else q = 6;
-        q = int(std::min<int64_t>(q, m));
-    }
-    if (w == 0) w = 32;
-    if (alpha == 0) alpha = std::min(12, alpha_max(w));
+// Built-in priors when the caller leaves a parameter at 0, keyed by the
+// pattern length and the number of distinct bytes of x (a stand-in for the
+// alphabet of the text). Section 4 reports best variants with q between 3 and
+// 8 and alpha 11-12; on gfx950 the fastest choices measured on iid texts over
+// 4 and 64 symbols were: longer q-grams for small alphabets, smaller tables
+// (alpha 11, 16-bit words: more workgroups fit in LDS) for m up to 128. A
+// tuned entry (hc_autotune) takes precedence.
+void default_params(int64_t m, int distinct, int &q, int &alpha, int &w) {
+    const bool small_sigma = distinct <= 4;
+    int pq, pa, pw;
+    if (m <= 2) { pq = 2; pa = 8; pw = 8; }
+    else if (m <= 4) { pq = (small_sigma && distinct < 4) ? 3 : 2; pa = 12; pw = 32; }
+    else if (m <= 8) { pq = small_sigma ? 5 : 3; pa = 12; pw = 32; }
+    else if (m <= 16) { pq = small_sigma ? 5 : 4; pa = 12; pw = 32; }
+    else if (m <= 128) { pq = 5; pa = 11; pw = 16; }
+    else if (m <= 256) { pq = 5; pa = 12; pw = 32; }
+    else { pq = 6; pa = 12; pw = 32; }
+    if (q == 0) q = int(std::min<int64_t>(pq, m));
+    if (w == 0) w = pw;
+    if (alpha == 0) alpha = std::min(pa, alpha_max(w));
+}
+
+int distinct_bytes(const uint8_t *x, int64_t m) {
+    bool seen[256] = {false};
+    int d = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (!seen[x[i]]) {
+            seen[x[i]] = true;
+            ++d;
+        }
+    return d;
 }
 
 static inline uint32_t qgram_hash(const uint8_t *u, int q, int s, uint32_t mask) {

@@ -113,7 +113,7 @@ hc_status pattern_on_device(hc_pattern *p, const DeviceCopy **out) {
 hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req) {
     hc_launch lc{0, 0, 0, 0};
     if (req) lc = *req;
-    if (lc.segment <= 0) lc.segment = 132;   // tile of 33792 starts; 132/4 is odd
+    if (lc.segment <= 0) lc.segment = 100;   // tile of 25600 starts; 100/4 is odd
     if (lc.schedule == HC_SCHED_AUTO) lc.schedule = HC_SCHED_SEGMENT;
     if (lc.variant == HC_VARIANT_AUTO) lc.variant = HC_VARIANT_HC;
     (void)p;
@@ -145,7 +145,7 @@ hc_status hc_preprocess(const uint8_t *x, int64_t m, const hc_params *params, hc
     if (!x || m < 1 || m > kMaxM) return HC_EINVAL;
     int q = params ? params->q : 0, alpha = params ? params->alpha : 0, w = params ? params->w : 0;
     if (q < 0 || alpha < 0 || w < 0) return HC_EINVAL;
-    default_params(m, q, alpha, w);
+    default_params(m, distinct_bytes(x, m), q, alpha, w);
     hc_status st = validate_params(m, q, alpha, w);
     if (st != HC_OK) return st;
     hc_pattern *p = new (std::nothrow) hc_pattern();

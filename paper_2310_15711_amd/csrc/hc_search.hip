@@ -46,7 +46,7 @@ struct SearchArgs {
     uint32_t *spill;     // per tile: the occurrence bitmap, when denser
 };
 
-template <int Q, typename WT, int SCHED>
+template <int Q, typename WT, int SCHED, int K>
 __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     const LdsLayout L = lds_layout(A.tile, A.m, A.table_bytes, 0);
@@ -120,8 +120,8 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
             while (true) {
                 uint32_t *npark = &misc[10 + (round & 1u)];
                 if (running) {
-                    running = !hc_segment<Q, WT>(t32, tb_cur, F, P, J0, jmid, J1, jhi, bm, any, park,
-                                                 npark, &myslot);
+                    running = !hc_segment<Q, WT, K>(t32, tb_cur, F, P, J0, jmid, J1, jhi, bm, any,
+                                                    park, npark, &myslot);
                     // `running` now means: parked, resumes after the walk is finished
                 }
                 lds_barrier();
@@ -207,6 +207,29 @@ struct EmitArgs {
     int64_t *d_count;
 };
 
+// Sum of counts[0..r) by one workgroup, 16-byte loads, all issued together.
+__device__ __forceinline__ uint32_t sum_counts(const uint32_t *counts, uint32_t r, uint32_t *lds_w) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nvec = r / 4u;
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(counts);
+    uint32_t part = 0;
+    for (uint32_t base = 0; base < nvec; base += 4u * kBlock) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = base + k * kBlock + tid;
+            v[k] = i < nvec ? c4[i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part += v[k].x + v[k].y + v[k].z + v[k].w;
+    }
+    if (tid < (r & 3u)) part += counts[nvec * 4u + tid];
+    uint32_t total;
+    (void)block_exclusive_scan(part, lds_w, &total);
+    lds_barrier();
+    return total;
+}
+
 __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
     __shared__ uint32_t lds_w[4];
     __shared__ uint32_t cnt[kBlock];
@@ -217,57 +240,50 @@ __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
         if (blockIdx.x == 0 && tid == 0) *A.d_count = 0;
         return;
     }
+    // this workgroup's tiles (at most 256)
     const uint32_t r0 = min(A.n_tiles, blockIdx.x * A.per), r1 = min(A.n_tiles, r0 + A.per);
     if (r0 >= r1) return;
-    uint32_t part = 0;
-    for (uint32_t i = tid; i < r0; i += kBlock) part += A.counts[i];
-    uint32_t before;
-    (void)block_exclusive_scan(part, lds_w, &before);
+    const uint32_t nc = r1 - r0;
+    const uint32_t mycnt = tid < nc ? A.counts[r0 + tid] : 0u;
+    uint32_t range_total;
+    const uint32_t myoff = block_exclusive_scan(mycnt, lds_w, &range_total);
+    cnt[tid] = mycnt;
+    off[tid] = myoff;
     lds_barrier();
-    int64_t prefix = before;
-    // this workgroup's tiles, up to 256 at a time
-    for (uint32_t c0 = r0; c0 < r1; c0 += kBlock) {
-        const uint32_t nc = min(kBlock, r1 - c0);
-        const uint32_t mycnt = tid < nc ? A.counts[c0 + tid] : 0u;
-        uint32_t chunk_total;
-        const uint32_t myoff = block_exclusive_scan(mycnt, lds_w, &chunk_total);
-        cnt[tid] = mycnt;
-        off[tid] = myoff;
-        lds_barrier();
-        for (uint32_t j = 0; j < nc; ++j) {
-            const uint32_t c = cnt[j];
-            if (c == 0u) continue;
-            const uint32_t t = c0 + j;
-            const uint64_t tile_lo = uint64_t(t) * A.tile;
-            const int64_t base = prefix + off[j];
-            if (c <= kSlot) {
-                if (tid < c && base + tid < A.cap)
-                    A.out[base + tid] = int64_t(tile_lo + A.slots[uint64_t(t) * kSlot + tid]);
-            } else {
-                const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
-                const uint32_t words = (S + 31u) / 32u;
-                const uint32_t wpt = (words + kBlock - 1u) / kBlock;
-                const uint32_t w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
-                const uint32_t *sb = A.spill + uint64_t(t) * tile_words;
-                uint32_t k = 0;
-                for (uint32_t i = w0; i < w1; ++i) k += __popc(sb[i]);
-                uint32_t tot;
-                int64_t idx = base + block_exclusive_scan(k, lds_w, &tot);
-                lds_barrier();
-                for (uint32_t i = w0; i < w1 && idx < A.cap; ++i) {
-                    uint32_t b = sb[i];
-                    while (b && idx < A.cap) {
-                        const uint32_t bit = __builtin_ctz(b);
-                        b &= b - 1u;
-                        A.out[idx++] = int64_t(tile_lo + i * 32u + bit);
-                    }
+    const bool last = r1 == A.n_tiles;
+    if (range_total == 0u && !last) return;   // nothing to write, and no total to report
+    const int64_t prefix = sum_counts(A.counts, r0, lds_w);
+    for (uint32_t j = 0; j < nc; ++j) {
+        const uint32_t c = cnt[j];
+        if (c == 0u) continue;
+        const uint32_t t = r0 + j;
+        const uint64_t tile_lo = uint64_t(t) * A.tile;
+        const int64_t base = prefix + off[j];
+        if (c <= kSlot) {
+            if (tid < c && base + tid < A.cap)
+                A.out[base + tid] = int64_t(tile_lo + A.slots[uint64_t(t) * kSlot + tid]);
+        } else {
+            const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
+            const uint32_t words = (S + 31u) / 32u;
+            const uint32_t wpt = (words + kBlock - 1u) / kBlock;
+            const uint32_t w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
+            const uint32_t *sb = A.spill + uint64_t(t) * tile_words;
+            uint32_t k = 0;
+            for (uint32_t i = w0; i < w1; ++i) k += __popc(sb[i]);
+            uint32_t tot;
+            int64_t idx = base + block_exclusive_scan(k, lds_w, &tot);
+            lds_barrier();
+            for (uint32_t i = w0; i < w1 && idx < A.cap; ++i) {
+                uint32_t b = sb[i];
+                while (b && idx < A.cap) {
+                    const uint32_t bit = __builtin_ctz(b);
+                    b &= b - 1u;
+                    A.out[idx++] = int64_t(tile_lo + i * 32u + bit);
                 }
             }
         }
-        prefix += chunk_total;
-        lds_barrier();
     }
-    if (r1 == A.n_tiles && tid == 0) *A.d_count = prefix;
+    if (last && tid == 0) *A.d_count = prefix + range_total;
 }
 
 // ----------------------------------------------------------------------------
@@ -276,32 +292,37 @@ __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
 
 using KernelFn = void (*)(SearchArgs);
 
+// Look-ahead of the search loop: with short shifts most attempts are cheap
+// and independent, so several are fetched together.
+static int lookahead_for(uint32_t shift) { return shift <= 12 ? 4 : 1; }
+
 template <int Q, typename WT>
-static KernelFn pick_sched(int sched) {
-    return sched == HC_SCHED_WAVE ? hc_search_kernel<Q, WT, HC_SCHED_WAVE>
-                                  : hc_search_kernel<Q, WT, HC_SCHED_SEGMENT>;
+static KernelFn pick_sched(int sched, int K) {
+    if (sched == HC_SCHED_WAVE) return hc_search_kernel<Q, WT, HC_SCHED_WAVE, 1>;
+    return K == 4 ? hc_search_kernel<Q, WT, HC_SCHED_SEGMENT, 4>
+                  : hc_search_kernel<Q, WT, HC_SCHED_SEGMENT, 1>;
 }
 
 template <int Q>
-static KernelFn pick_w(int w, int sched) {
+static KernelFn pick_w(int w, int sched, int K) {
     switch (w) {
-        case 8: return pick_sched<Q, uint8_t>(sched);
-        case 16: return pick_sched<Q, uint16_t>(sched);
-        case 32: return pick_sched<Q, uint32_t>(sched);
-        default: return pick_sched<Q, uint64_t>(sched);
+        case 8: return pick_sched<Q, uint8_t>(sched, K);
+        case 16: return pick_sched<Q, uint16_t>(sched, K);
+        case 32: return pick_sched<Q, uint32_t>(sched, K);
+        default: return pick_sched<Q, uint64_t>(sched, K);
     }
 }
 
-static KernelFn pick_kernel(int q, int w, int sched) {
+static KernelFn pick_kernel(int q, int w, int sched, int K) {
     switch (q) {
-        case 1: return pick_w<1>(w, sched);
-        case 2: return pick_w<2>(w, sched);
-        case 3: return pick_w<3>(w, sched);
-        case 4: return pick_w<4>(w, sched);
-        case 5: return pick_w<5>(w, sched);
-        case 6: return pick_w<6>(w, sched);
-        case 7: return pick_w<7>(w, sched);
-        default: return pick_w<8>(w, sched);
+        case 1: return pick_w<1>(w, sched, K);
+        case 2: return pick_w<2>(w, sched, K);
+        case 3: return pick_w<3>(w, sched, K);
+        case 4: return pick_w<4>(w, sched, K);
+        case 5: return pick_w<5>(w, sched, K);
+        case 6: return pick_w<6>(w, sched, K);
+        case 7: return pick_w<7>(w, sched, K);
+        default: return pick_w<8>(w, sched, K);
     }
 }
 
@@ -348,7 +369,7 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
     if (st != HC_OK) return st;
 
-    KernelFn fn = pick_kernel(pd.q, pd.w, lc.schedule);
+    KernelFn fn = pick_kernel(pd.q, pd.w, lc.schedule, lookahead_for(m - uint32_t(pd.q) + 1u));
     int per_cu = occupancy(fn, L.total);
     if (lc.wg_per_cu > 0) per_cu = std::min(per_cu, int(lc.wg_per_cu));
     uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, int64_t(di.cus) * per_cu)));
@@ -380,7 +401,10 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     EmitArgs E;
     E.n_tiles = n_tiles;
     E.tile = tile;
-    const uint32_t emit_grid = std::max<uint32_t>(1, std::min<uint32_t>(n_tiles, uint32_t(di.cus) * 2u));
+    // at most 256 tiles per workgroup of the ordered output
+    const uint32_t emit_grid = std::max<uint32_t>(
+        std::max<uint32_t>(1, (n_tiles + kBlock - 1) / kBlock),
+        std::min<uint32_t>(n_tiles, uint32_t(di.cus) * 2u));
     E.per = (n_tiles + emit_grid - 1) / emit_grid;
     E.starts = starts;
     E.counts = ws->counts;
