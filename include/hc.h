@@ -151,7 +151,7 @@ hc_status hc_search_async(const hc_pattern *p, const uint8_t *d_y, int64_t n,
  * n_pairs + 1 entries. *total (host) = all occurrences. total > cap ->
  * HC_EOVERFLOW; then d_pair_off still holds the full offsets but d_pos holds
  * only positions whose slot is < cap. Synchronises `stream`.
- *   params  NULL = chosen per pattern length by the autotuner / priors.
+ *   params  NULL = q chosen per pattern (autotuner / priors), alpha = 12, w = 16.
  */
 typedef struct {
     const uint8_t *d_text;
@@ -168,6 +168,25 @@ typedef struct {
 hc_status hc_search_batched(const hc_batch *batch, const hc_params *params,
                             int64_t *d_pos, int64_t cap, int64_t *d_pair_off,
                             int64_t *total, void *stream);
+
+/*
+ * Batch plans: hc_search_batched split in two, for batches searched many
+ * times. hc_batch_plan_create preprocesses every pattern (the word vectors of
+ * one batch share alpha and w; w must be 16 or 32 and 2^alpha * w / 8 at most
+ * 16 KiB, else HC_EINVAL; params->q, when set,
+ * applies to every pattern, capped at its length), groups the pairs by text
+ * and uploads the work list. The texts stay caller-owned and must outlive the
+ * plan. hc_batch_plan_run searches (results and errors as hc_search_batched)
+ * by replaying a HIP graph captured for its (d_pos, cap, d_pair_off, stream);
+ * runs of one plan must not overlap. hc_batch_plan_free releases the plan.
+ */
+typedef struct hc_batch_plan hc_batch_plan;
+
+hc_status hc_batch_plan_create(const hc_batch *batch, const hc_params *params,
+                               hc_batch_plan **out);
+hc_status hc_batch_plan_run(hc_batch_plan *plan, int64_t *d_pos, int64_t cap,
+                            int64_t *d_pair_off, int64_t *total, void *stream);
+void hc_batch_plan_free(hc_batch_plan *plan);
 
 /*
  * Serving: continuous batching of search requests against resident texts.

@@ -24,7 +24,8 @@ HC_VARIANT_AUTO, HC_VARIANT_HC, HC_VARIANT_SENTINEL, HC_VARIANT_SPARSE = 0, 1, 2
 # every symbol declared in include/hc.h
 EXPORTED = (
     "hc_preprocess", "hc_pattern_info", "hc_pattern_free", "hc_search", "hc_search_async",
-    "hc_search_batched", "hc_serve_create", "hc_serve_submit", "hc_serve_poll",
+    "hc_search_batched", "hc_batch_plan_create", "hc_batch_plan_run", "hc_batch_plan_free",
+    "hc_serve_create", "hc_serve_submit", "hc_serve_poll",
     "hc_serve_stats", "hc_serve_destroy", "hc_strerror",
 )
 
@@ -72,6 +73,9 @@ def lib():
         "hc_search": (i32, [p, p, i64, p, i64, P(i64), p]),
         "hc_search_async": (i32, [p, p, i64, p, i64, p, p, p]),
         "hc_search_batched": (i32, [P(hc_batch), p, p, i64, p, P(i64), p]),
+        "hc_batch_plan_create": (i32, [P(hc_batch), p, P(p)]),
+        "hc_batch_plan_run": (i32, [p, p, i64, p, P(i64), p]),
+        "hc_batch_plan_free": (None, [p]),
         "hc_serve_create": (i32, [p, p, i32, i64, p, P(p)]),
         "hc_serve_submit": (i32, [p, i32, p, i64, P(u64)]),
         "hc_serve_poll": (i32, [p, u64, p, i64, P(i64), i32]),
@@ -214,9 +218,7 @@ def find_all(p: Pattern, y, cap: int = 1 << 16, stream=None):
         cap = cnt
 
 
-def hc_search_batched(d_text, text_off: Sequence[int], patterns: Sequence[bytes],
-                      pair_pat, pair_text, d_pos, d_pair_off, params=None, stream=None):
-    """Returns (status, total). text_off has n_texts + 1 entries."""
+def _make_batch(d_text, text_off, patterns, pair_pat, pair_text):
     to = np.ascontiguousarray(text_off, dtype=np.int64)
     pat_bytes = b"".join(patterns)
     po = np.zeros(len(patterns) + 1, dtype=np.int64)
@@ -227,6 +229,13 @@ def hc_search_batched(d_text, text_off: Sequence[int], patterns: Sequence[bytes]
     b = hc_batch(_dev_ptr(d_text, "torch.uint8") if d_text.numel() else None, to.ctypes.data,
                  len(to) - 1, pb.ctypes.data, po.ctypes.data, len(patterns),
                  pp.ctypes.data, pt.ctypes.data, len(pp))
+    return b, (to, po, pb, pp, pt)   # keep the host arrays alive with the struct
+
+
+def hc_search_batched(d_text, text_off: Sequence[int], patterns: Sequence[bytes],
+                      pair_pat, pair_text, d_pos, d_pair_off, params=None, stream=None):
+    """Returns (status, total). text_off has n_texts + 1 entries."""
+    b, _keep = _make_batch(d_text, text_off, patterns, pair_pat, pair_text)
     total = ctypes.c_int64()
     pr = _params(params)
     cap = int(d_pos.numel()) if d_pos is not None else 0
@@ -236,6 +245,36 @@ def hc_search_batched(d_text, text_off: Sequence[int], patterns: Sequence[bytes]
                                  _stream_ptr(stream))
     _check(st, "hc_search_batched", ok=(HC_OK, HC_EOVERFLOW))
     return st, total.value
+
+
+class BatchPlan:
+    """hc_batch_plan_create / hc_batch_plan_run / hc_batch_plan_free."""
+
+    def __init__(self, d_text, text_off, patterns, pair_pat, pair_text, params=None):
+        self._text = d_text
+        b, keep = _make_batch(d_text, text_off, patterns, pair_pat, pair_text)
+        out = ctypes.c_void_p()
+        pr = _params(params)
+        _check(lib().hc_batch_plan_create(ctypes.byref(b), ctypes.byref(pr) if pr is not None else None,
+                                          ctypes.byref(out)), "hc_batch_plan_create")
+        self.handle = out
+        self.n_pairs = len(keep[3])
+
+    def run(self, d_pos, d_pair_off, stream=None):
+        """Returns (status, total)."""
+        total = ctypes.c_int64()
+        cap = int(d_pos.numel()) if d_pos is not None else 0
+        st = lib().hc_batch_plan_run(self.handle, _dev_ptr(d_pos, "torch.int64") if cap else None, cap,
+                                     _dev_ptr(d_pair_off, "torch.int64"), ctypes.byref(total),
+                                     _stream_ptr(stream))
+        _check(st, "hc_batch_plan_run", ok=(HC_OK, HC_EOVERFLOW))
+        return st, total.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hc_batch_plan_free(h)
+            self.handle = None
 
 
 class Server:

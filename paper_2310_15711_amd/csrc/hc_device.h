@@ -13,6 +13,7 @@
 namespace hc {
 
 constexpr int kWave = 64;
+constexpr uint32_t kThreads = 256;   // threads per workgroup of the search kernels
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -442,6 +443,84 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t c, uint32_t *l
     }
     *total = all;
     return before + incl - c;
+}
+
+// ----------------------------------------------------------------------------
+// One tile searched for one pattern: the searching loop of every lane over
+// its block of window starts (rounds separated by LDS barriers while lanes
+// have parked chain walks), then the comparison of the candidate windows with
+// x. Leaves the occurrences in the bitmap `bm` (tile-relative starts) and
+// returns the tile's count, this thread's exclusive prefix and its bitmap
+// word range. Every thread of the workgroup calls it. `it` and `round` are
+// per-workgroup counters that select double-buffered LDS flags; misc[8..11]
+// hold those flags and misc[0..3] the scan.
+// ----------------------------------------------------------------------------
+struct TileResult {
+    uint32_t total, mine, w0, w1;
+};
+
+template <int Q, typename WT, int K>
+__device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                  const WT *__restrict__ F,
+                                                  const uint32_t *__restrict__ x32,
+                                                  const PatternView &P, uint32_t S, uint32_t seg,
+                                                  uint32_t *bm, Parked *park, uint32_t *misc,
+                                                  uint32_t &it, uint32_t &round) {
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    uint32_t *any = &misc[8 + (it & 1u)];
+    {
+        const uint32_t lo = min(S, tid * seg), hi = min(S, lo + seg);
+        const uint32_t jlo = lo + P.m - 1u, jhi = hi + P.m - 1u;
+        const uint32_t jmid = jlo + ((jhi - jlo) >> 1);
+        uint32_t J0 = jlo, J1 = jmid, myslot = kParkCap;
+        bool running = lo < hi;
+        while (true) {
+            uint32_t *npark = &misc[10 + (round & 1u)];
+            if (running)   // afterwards: true when the lane parked a walk
+                running = !hc_segment<Q, WT, K>(t32, tb, F, P, J0, jmid, J1, jhi, bm, any, park,
+                                                npark, &myslot);
+            lds_barrier();
+            const uint32_t np = min(*npark, kParkCap);
+            if (tid == 0) misc[10 + ((round + 1u) & 1u)] = 0u;
+            ++round;
+            if (np == 0u) break;
+            // long chain walks, finished by whole wavefronts
+            for (uint32_t i = wid; i < np; i += kThreads / kWave) {
+                const Parked pk = park[i];
+                const uint32_t next = hc_chain_wave<Q, WT>(t32, tb, F, P, pk, lane, bm, any);
+                if (lane == 0) park[i].J = next;
+            }
+            lds_barrier();
+            if (running) {
+                const Parked &pk = park[myslot];
+                if ((pk.owner & 1u) == 0u) J0 = pk.J; else J1 = pk.J;
+                myslot = kParkCap;
+            }
+        }
+    }
+    const bool has = *any != 0u;
+    if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;   // flag of the next call
+    ++it;
+    TileResult R{0u, 0u, 0u, 0u};
+    if (!has) return R;                           // most tiles: no candidate at all
+    // compare candidates with x; count this thread's share of the tile
+    const uint32_t words = (S + 31u) / 32u;
+    const uint32_t wpt = (words + kThreads - 1u) / kThreads;
+    R.w0 = min(words, tid * wpt);
+    R.w1 = min(words, R.w0 + wpt);
+    uint32_t c = 0;
+    for (uint32_t i = R.w0; i < R.w1; ++i) {
+        uint32_t b = bm[i], keep = b;
+        while (b) {
+            const uint32_t bit = __builtin_ctz(b);
+            b &= b - 1u;
+            if (!window_equals(t32, tb + i * 32u + bit, x32, P.m)) keep &= ~(1u << bit);
+        }
+        bm[i] = keep;
+        c += __popc(keep);
+    }
+    R.mine = block_exclusive_scan(c, misc, &R.total);
+    return R;
 }
 
 }  // namespace hc

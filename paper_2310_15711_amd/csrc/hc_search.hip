@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     __syncthreads();
     uint32_t round = 0;
     uint32_t it = 0;
-    for (uint32_t t = blockIdx.x; t < A.n_tiles; t += G, ++it) {
+    for (uint32_t t = blockIdx.x; t < A.n_tiles; t += G) {
         const uint64_t tile_lo = uint64_t(t) * A.tile;
         const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
         stage_commit(stage, t8);
@@ -104,73 +104,43 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
             const uint32_t Sn = uint32_t(min<uint64_t>(A.tile, A.starts - lo));
             tb = stage_issue(A.y, lo, lo + Sn + A.m - 1u, stage);
         }
-        uint32_t *any = &misc[8 + (it & 1u)];
+        uint32_t total, mine, w0, w1;
         if constexpr (SCHED == HC_SCHED_WAVE) {
+            uint32_t *any = &misc[8 + (it & 1u)];
             const uint32_t per = (S + 3u) / 4u;
             const uint32_t lo = min(S, wid * per), hi = min(S, lo + per);
             hc_wave<Q, WT>(t32, tb_cur, F, P, lo, hi, bm, lane, any);
             lds_barrier();
+            const bool has = *any != 0u;
+            if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;
+            ++it;
+            total = mine = w0 = w1 = 0u;
+            if (has) {
+                const uint32_t words = (S + 31u) / 32u;
+                const uint32_t wpt = (words + kBlock - 1u) / kBlock;
+                w0 = min(words, tid * wpt);
+                w1 = min(words, w0 + wpt);
+                uint32_t c = 0;
+                for (uint32_t i = w0; i < w1; ++i) {
+                    uint32_t b = bm[i], keep = b;
+                    while (b) {
+                        const uint32_t bit = __builtin_ctz(b);
+                        b &= b - 1u;
+                        if (!window_equals(t32, tb_cur + i * 32u + bit, x32, A.m)) keep &= ~(1u << bit);
+                    }
+                    bm[i] = keep;
+                    c += __popc(keep);
+                }
+                mine = block_exclusive_scan(c, misc, &total);
+            }
         } else {
-            // the lane's window ends, in two halves searched side by side
-            const uint32_t lo = min(S, tid * A.seg), hi = min(S, lo + A.seg);
-            const uint32_t jlo = lo + A.m - 1u, jhi = hi + A.m - 1u;
-            const uint32_t jmid = jlo + ((jhi - jlo) >> 1);
-            uint32_t J0 = jlo, J1 = jmid, myslot = kParkCap;
-            bool running = lo < hi;
-            while (true) {
-                uint32_t *npark = &misc[10 + (round & 1u)];
-                if (running) {
-                    running = !hc_segment<Q, WT, K>(t32, tb_cur, F, P, J0, jmid, J1, jhi, bm, any,
-                                                    park, npark, &myslot);
-                    // `running` now means: parked, resumes after the walk is finished
-                }
-                lds_barrier();
-                const uint32_t np = min(*npark, kParkCap);
-                if (tid == 0) misc[10 + ((round + 1u) & 1u)] = 0u;
-                ++round;
-                if (np == 0u) break;
-                // long chain walks, finished by whole wavefronts
-                for (uint32_t i = wid; i < np; i += kBlock / kWave) {
-                    const Parked pk = park[i];
-                    const uint32_t next = hc_chain_wave<Q, WT>(t32, tb_cur, F, P, pk, lane, bm, any);
-                    if (lane == 0) park[i].J = next;
-                }
-                lds_barrier();
-                if (running) {
-                    const Parked &pk = park[myslot];
-                    if ((pk.owner & 1u) == 0u) J0 = pk.J; else J1 = pk.J;
-                    myslot = kParkCap;
-                }
-            }
+            const TileResult R = search_tile<Q, WT, K>(t32, tb_cur, F, x32, P, S, A.seg, bm, park,
+                                                       misc, it, round);
+            total = R.total;
+            mine = R.mine;
+            w0 = R.w0;
+            w1 = R.w1;
         }
-
-        // most tiles hold no candidate at all: then nothing to compare or write
-        if (misc[8 + (it & 1u)] == 0u) {
-            if (tid == 0) {
-                A.counts[t] = 0u;
-                misc[8 + ((it + 1u) & 1u)] = 0u;   // flag of the next tile
-            }
-            continue;
-        }
-        if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;
-
-        // compare candidates with x; count this thread's share of the tile
-        const uint32_t words = (S + 31u) / 32u;
-        const uint32_t wpt = (words + kBlock - 1u) / kBlock;
-        const uint32_t w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
-        uint32_t c = 0;
-        for (uint32_t i = w0; i < w1; ++i) {
-            uint32_t b = bm[i], keep = b;
-            while (b) {
-                const uint32_t bit = __builtin_ctz(b);
-                b &= b - 1u;
-                if (!window_equals(t32, tb_cur + i * 32u + bit, x32, A.m)) keep &= ~(1u << bit);
-            }
-            bm[i] = keep;
-            c += __popc(keep);
-        }
-        uint32_t total;
-        const uint32_t mine = block_exclusive_scan(c, misc, &total);
         if (tid == 0) A.counts[t] = total;
         if (total != 0u) {
             if (total <= kSlot) {
