@@ -199,6 +199,8 @@ def hc_search_async(p: Pattern, y, out, d_count, launch=None, stream=None, n=Non
     if y_ptr is None:
         y_ptr = _dev_ptr(y, "torch.uint8") if y.numel() else None
         n = int(y.numel()) if n is None else n
+    if out is not None and out.numel() == 0:
+        cap = 0
     st = lib().hc_search_async(p.handle, y_ptr, int(n),
                                _dev_ptr(out, "torch.int64") if cap else None, cap,
                                _dev_ptr(d_count, "torch.int64"),
