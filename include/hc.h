@@ -190,20 +190,30 @@ void hc_batch_plan_free(hc_batch_plan *plan);
 
 /*
  * Serving: continuous batching of search requests against resident texts.
- * hc_serve_create registers n_texts device texts (caller-owned, must outlive
- * the server), a device-memory budget in bytes for in-flight requests
- * (pattern tables plus result slots), and optional fixed params (NULL =
- * library choice). A scheduler thread admits queued requests while the
- * budget allows, groups the active requests by text, and scans each text in
- * chunks, so a request that arrives while others run joins at the next chunk
- * and finishes after one full cycle over its text.
- * hc_serve_submit copies x and returns a request id (thread-safe).
+ * hc_serve_create registers n_texts device texts (caller-owned, written
+ * before the call, must outlive the server), a device-memory budget in bytes
+ * for in-flight requests, and optional params shared by every request (as
+ * for batch plans: NULL = q per pattern, alpha 12, w 16; w 16 or 32, tables
+ * up to 16 KiB). Each in-flight request holds its table, a 4128-byte pattern
+ * slot and room for 4096 positions per step (32 KiB); a budget below one
+ * request's share gives HC_EINVAL. A scheduler thread admits queued requests
+ * (FIFO) while the budget allows, and runs steps: one batched launch searches
+ * the next 8 MiB chunk of every text that has active requests, for all of
+ * them. A request that arrives while others run joins at the next step and
+ * finishes after one full cycle over its text. Results are the same as
+ * hc_search's, whatever else is in flight.
+ * hc_serve_submit preprocesses and copies x (1 <= m <= 4096) and returns a
+ * request id (thread-safe).
  * hc_serve_poll waits up to timeout_us (0 = do not wait) and returns
  * HC_EAGAIN while the request runs; when done it copies min(count, cap)
- * ascending positions to host `out`, sets *count, releases the request and
- * returns HC_OK (or HC_EOVERFLOW when count > cap, the request is still
- * released). Stats: latency percentiles of completed requests (submit to
- * completion) and aggregate text bytes searched per second of server time.
+ * ascending positions to host `out` and sets *count. With count <= cap it
+ * releases the request and returns HC_OK; otherwise it returns HC_EOVERFLOW
+ * and keeps the request, so a second poll with cap >= count gets all of it.
+ * An unknown or released id gives HC_EINVAL; a failed step fails its requests
+ * with that step's status (HC_EHIP, HC_ENOMEM) and later submits with it too.
+ * Stats: latency percentiles of completed requests (submit to completion),
+ * aggregate text bytes searched (summed over requests) per second of time the
+ * scheduler spent in steps, and the number of completed requests.
  */
 typedef struct hc_server hc_server;
 

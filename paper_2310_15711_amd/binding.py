@@ -301,7 +301,8 @@ class Server:
         return rid.value
 
     def poll(self, req_id: int, cap: int = 1 << 16, timeout_us: int = 0):
-        """None while running; else (status, positions as numpy int64)."""
+        """None while running; else (status, positions as numpy int64, count).
+        HC_EOVERFLOW leaves the request in place (poll again with cap >= count)."""
         out = np.empty(max(cap, 1), dtype=np.int64)
         cnt = ctypes.c_int64()
         st = lib().hc_serve_poll(self.handle, ctypes.c_uint64(req_id), out.ctypes.data, int(cap),
@@ -310,6 +311,23 @@ class Server:
             return None
         _check(st, "hc_serve_poll", ok=(HC_OK, HC_EOVERFLOW))
         return st, out[:min(cnt.value, cap)].copy(), cnt.value
+
+    def result(self, req_id: int, timeout_s: float = 60.0) -> np.ndarray:
+        """Waits for a request and returns all of its positions."""
+        import time
+
+        end = time.monotonic() + timeout_s
+        cap = 1 << 12
+        while True:
+            r = self.poll(req_id, cap=cap, timeout_us=100_000)
+            if r is not None:
+                st, pos, cnt = r
+                if st == HC_OK:
+                    return pos
+                cap = cnt   # overflow: the request is kept
+                continue
+            if time.monotonic() > end:
+                raise TimeoutError(f"request {req_id} not done after {timeout_s} s")
 
     def stats(self) -> dict:
         p50, p99, gbps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

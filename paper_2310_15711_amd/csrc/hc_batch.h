@@ -1,0 +1,100 @@
+// Host interface of the batched searching kernel, shared by the batch plans
+// of the C ABI and the serving loop. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "hc_internal.h"
+
+namespace hc {
+
+struct BPat {            // one pattern of the batch, as the kernel reads it
+    uint32_t m, q, s, mask, hv;
+    uint32_t x_off;      // byte offset of x in the packed patterns (16-aligned)
+    uint32_t pad0, pad1;
+};
+
+struct BItem {           // one work item
+    uint32_t text, tile, g0, g1;   // group = glist[g0, g1), sorted by m descending
+};
+
+struct TextView {        // one text as a batch sees it
+    const uint8_t *ptr;
+    uint64_t len;          // bytes readable from ptr
+    uint64_t start_limit;  // only window starts below this are searched
+};
+
+// Owned device allocation that only grows.
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DeviceBuf() = default;
+    DeviceBuf(const DeviceBuf &) = delete;
+    DeviceBuf &operator=(const DeviceBuf &) = delete;
+    ~DeviceBuf();
+    hc_status ensure(size_t b);
+    hc_status upload(const void *src, size_t b, hipStream_t s);   // async on s
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// What the host decides for one batch: texts, patterns, pairs and work items.
+struct BatchHost {
+    std::vector<TextView> views;
+    std::vector<BPat> pats;
+    std::vector<uint32_t> glist;      // (pattern, pair) per group member
+    std::vector<uint64_t> pair_base;  // n_pairs + 1
+    std::vector<BItem> items;
+};
+
+// Device side of a batch: geometry, uploaded descriptors and result buffers.
+struct BatchDev {
+    uint32_t tile = 0, seg = 100, table_bytes = 0, max_m = 1, w = 16, lds = 0, max_grid = 0;
+    uint32_t n_pairs = 0, n_items = 0, grid = 0, nb = 0;
+    uint64_t n_entries = 0, scratch_cap = 0;
+    const uint8_t *Fs = nullptr;   // table_bytes per pattern index
+    const uint8_t *xs = nullptr;   // pattern bytes at BPat::x_off
+    size_t Fs_bytes = 0, xs_bytes = 0;
+    DeviceBuf views, pats, items, glist, pair_base, counts, toff, temp, ctl, tot, bsum, grand;
+};
+
+// Common table shape of a batch (w in {16, 32}; tables up to 16 KiB).
+hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &table_bytes);
+
+// Tile size, LDS and grid bound for patterns up to max_m bytes.
+hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint32_t w);
+
+// Preprocesses np patterns (CSR pat/pat_off) into packed tables and bytes.
+hc_status pack_patterns(const uint8_t *pat, const int64_t *pat_off, int32_t np, const hc_params *params,
+                        int alpha, int w, uint32_t table_bytes, std::vector<BPat> &bp,
+                        std::vector<uint8_t> &Fh, std::vector<uint8_t> &Xh, uint32_t &max_m);
+
+// One pattern's descriptor, table and bytes (for pools that place x themselves).
+hc_status pack_one(const uint8_t *x, int64_t m, int q_req, int alpha, int w, uint32_t table_bytes,
+                   BPat &bp, uint8_t *F_out);
+
+// Groups the (pattern, text) pairs into work items (views and pats already set).
+void batch_build(BatchHost &H, const std::vector<std::pair<uint32_t, uint32_t>> &pairs, uint32_t tile,
+                 uint32_t group);
+
+// Checks that every index the kernel derives from H stays inside the views,
+// pattern tables, pattern bytes and per-pair entries (HC_EINVAL otherwise).
+hc_status batch_check(const BatchHost &H, const BatchDev &D);
+
+// Checks H (batch_check), uploads descriptors on stream s and sizes the
+// result buffers.
+hc_status batch_upload(const BatchHost &H, BatchDev &D, hipStream_t s);
+
+// Enqueues the search, the CSR offsets (d_pair_off, n_pairs + 1 entries) and
+// the copy of at most cap positions into d_pos, all on stream s.
+hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pair_off, hipStream_t s);
+
+// After a run reported scratch overflow: room for `total` positions.
+hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total);
+
+constexpr uint32_t kBatchGroup = 128;   // patterns searched per staged tile
+
+}  // namespace hc

@@ -21,25 +21,15 @@
 #include <numeric>
 #include <vector>
 
+#include "hc_batch.h"
 #include "hc_device.h"
 #include "hc_internal.h"
 #include "hc_runtime.h"
 
 namespace hc {
 
-struct BPat {            // one pattern of the batch, as the kernel reads it
-    uint32_t m, q, s, mask, hv;
-    uint32_t x_off;      // byte offset of x in the packed patterns (16-aligned)
-    uint32_t pad0, pad1;
-};
-
-struct BItem {           // one work item
-    uint32_t text, tile, g0, g1;   // group = glist[g0, g1), sorted by m descending
-};
-
 struct BatchArgs {
-    const uint8_t *text;           // all texts
-    const uint64_t *text_off;      // n_texts + 1
+    const TextView *texts;
     const BPat *pats;
     const uint8_t *xs;
     const uint8_t *Fs;             // table_bytes per pattern
@@ -162,14 +152,14 @@ __global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
         // the next ticket travels while this item is searched (two slots: the
         // previous one may still be read by threads of this workgroup)
         if (tid == 0) misc[12 + (k & 1u)] = uint32_t(atomicAdd(&A.ctl[0], 1ull));
-        const uint64_t tbase = A.text_off[W.text];
-        const uint64_t n_t = A.text_off[W.text + 1] - tbase;
+        const TextView tv = A.texts[W.text];
+        const uint64_t n_t = tv.len;
         const uint64_t tile_lo = uint64_t(W.tile) * A.tile;
         // longest pattern of the group comes first
         const uint32_t span = A.pats[A.glist[2 * W.g0]].m;
         const uint64_t g1 = min<uint64_t>(tile_lo + A.tile + span - 1u, n_t);
         Stage st;
-        const uint32_t tb = stage_issue(A.text + tbase, tile_lo, g1, st);
+        const uint32_t tb = stage_issue(tv.ptr, tile_lo, g1, st);
         PatStage ps;
         {
             const uint32_t p = A.glist[2 * W.g0];
@@ -187,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
                 const uint32_t pn = A.glist[2 * (gi + 1)];
                 pat_issue(A.Fs, A.xs, A.pats[pn], pn, A.table_bytes, L.x_bytes, ps);
             }
-            const uint64_t starts = n_t >= bp.m ? n_t - bp.m + 1u : 0u;
+            const uint64_t starts = min<uint64_t>(n_t >= bp.m ? n_t - bp.m + 1u : 0u, tv.start_limit);
             if (tile_lo >= starts) {   // uniform: no window of this pattern starts here
                 lds_barrier();
                 continue;
@@ -390,53 +380,30 @@ __global__ void hc_batch_reset(unsigned long long *ctl) {
     if (threadIdx.x < 4) ctl[threadIdx.x] = 0ull;
 }
 
+
 // ----------------------------------------------------------------------------
-// host side: the plan
+// host side
 // ----------------------------------------------------------------------------
 
-struct DeviceBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    ~DeviceBuf() {
-        if (p) (void)hipFree(p);
-    }
-    hc_status ensure(size_t b) {
-        if (bytes >= b && p) return HC_OK;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        if (hipMalloc(&p, std::max<size_t>(b, 16)) != hipSuccess) return HC_ENOMEM;
-        bytes = std::max<size_t>(b, 16);
-        return HC_OK;
-    }
-    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
-};
+DeviceBuf::~DeviceBuf() {
+    if (p) (void)hipFree(p);
+}
 
-}  // namespace hc
+hc_status DeviceBuf::ensure(size_t b) {
+    if (bytes >= b && p) return HC_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, std::max<size_t>(b, 16)) != hipSuccess) return HC_ENOMEM;
+    bytes = std::max<size_t>(b, 16);
+    return HC_OK;
+}
 
-using namespace hc;
-
-struct hc_batch_plan {
-    int device = -1;
-    uint32_t n_pairs = 0, n_items = 0, tile = 0, seg = 100, table_bytes = 0, max_m = 1, w = 16;
-    uint64_t n_entries = 0, scratch_cap = 0;
-    const uint8_t *d_text = nullptr;
-    DeviceBuf text_off, pats, xs, Fs, items, glist, pair_base, counts, toff, temp, ctl, tot, bsum, grand;
-    uint32_t grid = 0, lds = 0, nb = 0;
-    // graph for (d_pos, cap, d_pair_off, stream)
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    int64_t *g_pos = nullptr, *g_off = nullptr;
-    int64_t g_cap = -1;
-    hipStream_t g_stream = nullptr;
-    std::vector<unsigned long long> host_ctl;
-    ~hc_batch_plan() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-    }
-};
-
-namespace hc {
+hc_status DeviceBuf::upload(const void *src, size_t b, hipStream_t s) {
+    if (ensure(b) != HC_OK) return HC_ENOMEM;
+    if (b && hipMemcpyAsync(p, src, b, hipMemcpyHostToDevice, s) != hipSuccess) return HC_EHIP;
+    return HC_OK;
+}
 
 template <typename WT>
 static hc_status batch_occupancy(uint32_t lds, int *per_cu) {
@@ -448,59 +415,265 @@ static hc_status batch_occupancy(uint32_t lds, int *per_cu) {
     return HC_OK;
 }
 
-static hc_status enqueue_batch(hc_batch_plan *P, int64_t *d_pos, int64_t cap, int64_t *d_pair_off,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(hc_batch_reset, dim3(1), dim3(64), 0, s, P->ctl.as<unsigned long long>());
+hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &table_bytes) {
+    w = params && params->w ? params->w : 16;
+    alpha = params && params->alpha ? params->alpha : 12;
+    if ((w != 16 && w != 32) || alpha < 1 || alpha > alpha_max(w)) return HC_EINVAL;
+    table_bytes = uint32_t((size_t(1) << alpha) * size_t(w / 8));
+    table_bytes = std::max<uint32_t>(16, (table_bytes + 15u) & ~15u);
+    if (table_bytes > uint32_t(kFStage) * kThreads * 16u) return HC_EINVAL;   // <= 16 KiB
+    return HC_OK;
+}
+
+hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint32_t w) {
+    const DeviceInfo &di = device_info();
+    if (!di.ok) return HC_EHIP;
+    D.max_m = std::max<uint32_t>(max_m, 1);
+    D.table_bytes = table_bytes;
+    D.w = w;
+    // tiles as large as LDS allows
+    D.seg = 100;
+    D.tile = kThreads * D.seg;
+    LdsLayout L = lds_layout(D.tile, D.max_m, D.table_bytes, 0);
+    while ((L.total > di.max_lds_per_block || D.tile + D.max_m - 1u > stage_limit(kThreads)) && D.seg > 8) {
+        D.seg -= 4;
+        D.tile = kThreads * D.seg;
+        L = lds_layout(D.tile, D.max_m, D.table_bytes, 0);
+    }
+    if (L.total > di.max_lds_per_block) return HC_EINVAL;
+    D.lds = L.total;
+    int per_cu = 1;
+    hc_status st = w == 16 ? batch_occupancy<uint16_t>(D.lds, &per_cu) : batch_occupancy<uint32_t>(D.lds, &per_cu);
+    if (st != HC_OK) return st;
+    D.max_grid = uint32_t(di.cus) * uint32_t(per_cu);
+    return HC_OK;
+}
+
+hc_status pack_one(const uint8_t *x, int64_t m, int q_req, int alpha, int w, uint32_t table_bytes, BPat &bp,
+                   uint8_t *F_out) {
+    if (m < 1 || m > kMaxM) return HC_EINVAL;
+    int q = q_req, a = alpha, ww = w;
+    default_params(m, distinct_bytes(x, m), q, a, ww);
+    q = int(std::min<int64_t>(q, m));
+    if (validate_params(m, q, alpha, w) != HC_OK) return HC_EINVAL;
+    PatternData pd;
+    build_link_table(x, m, q, alpha, w, pd);
+    std::vector<uint8_t> packed = pack_table(pd);
+    if (packed.size() > table_bytes) return HC_EINVAL;
+    std::memset(F_out, 0, table_bytes);
+    std::memcpy(F_out, packed.data(), packed.size());
+    bp = BPat{uint32_t(m), uint32_t(q), uint32_t(pd.s), pd.mask, pd.hv, 0, 0, 0};
+    return HC_OK;
+}
+
+hc_status pack_patterns(const uint8_t *pat, const int64_t *pat_off, int32_t np, const hc_params *params,
+                        int alpha, int w, uint32_t table_bytes, std::vector<BPat> &bp, std::vector<uint8_t> &Fh,
+                        std::vector<uint8_t> &Xh, uint32_t &max_m) {
+    bp.assign(size_t(std::max(np, 1)), BPat{});
+    Fh.assign(size_t(std::max(np, 1)) * table_bytes, 0);
+    std::vector<uint32_t> xoff(size_t(np) + 1, 0);
+    int64_t mmax = 1;
+    for (int32_t i = 0; i < np; ++i) {
+        const int64_t m = pat_off[i + 1] - pat_off[i];
+        if (m < 1 || m > kMaxM) return HC_EINVAL;
+        xoff[i + 1] = xoff[i] + uint32_t(((m + 15) & ~int64_t(15)) + 32);
+        mmax = std::max(mmax, m);
+    }
+    // every pattern's bytes are read as a block of the longest pattern's size
+    Xh.assign(xoff[np] + size_t((mmax + 15) & ~int64_t(15)) + 64, 0);
+    max_m = uint32_t(mmax);
+    for (int32_t i = 0; i < np; ++i) {
+        const uint8_t *x = pat + pat_off[i];
+        const int64_t m = pat_off[i + 1] - pat_off[i];
+        hc_status st = pack_one(x, m, params ? params->q : 0, alpha, w, table_bytes, bp[i],
+                                Fh.data() + size_t(i) * table_bytes);
+        if (st != HC_OK) return st;
+        bp[i].x_off = xoff[i];
+        std::memcpy(Xh.data() + xoff[i], x, size_t(m));
+    }
+    return HC_OK;
+}
+
+void batch_build(BatchHost &H, const std::vector<std::pair<uint32_t, uint32_t>> &pairs, uint32_t tile,
+                 uint32_t group) {
+    const size_t nt = H.views.size();
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> by_text(std::max<size_t>(nt, 1));
+    H.pair_base.assign(pairs.size() + 1, 0);
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        const uint32_t p = pairs[k].first, t = pairs[k].second;
+        by_text[t].push_back({p, uint32_t(k)});
+        const uint64_t n_t = H.views[t].len, m = H.pats[p].m;
+        const uint64_t starts = std::min<uint64_t>(n_t >= m ? n_t - m + 1 : 0, H.views[t].start_limit);
+        H.pair_base[k + 1] = H.pair_base[k] + (starts + tile - 1) / tile;
+    }
+    // pairs grouped by text, longest pattern first; items dealt most expensive first
+    H.glist.clear();
+    struct ItemCost {
+        double cost;
+        BItem it;
+    };
+    std::vector<ItemCost> items;
+    for (size_t t = 0; t < nt; ++t) {
+        auto &v = by_text[t];
+        std::sort(v.begin(), v.end(),
+                  [&](const std::pair<uint32_t, uint32_t> &a, const std::pair<uint32_t, uint32_t> &c) {
+                      return H.pats[a.first].m > H.pats[c.first].m ||
+                             (H.pats[a.first].m == H.pats[c.first].m && a.second < c.second);
+                  });
+        const uint64_t n_t = std::min<uint64_t>(H.views[t].len, H.views[t].start_limit);
+        const uint32_t tiles = uint32_t((n_t + tile - 1) / tile);
+        for (size_t g = 0; g < v.size(); g += group) {
+            const uint32_t g0 = uint32_t(H.glist.size() / 2);
+            double per_byte = 0;
+            for (size_t j = g; j < std::min(v.size(), g + group); ++j) {
+                H.glist.push_back(v[j].first);
+                H.glist.push_back(v[j].second);
+                const BPat &q = H.pats[v[j].first];
+                per_byte += 1.0 / double(q.m - q.q + 1) + 0.02;
+            }
+            const uint32_t g1 = uint32_t(H.glist.size() / 2);
+            for (uint32_t tl = 0; tl < tiles; ++tl) {
+                const double bytes = double(std::min<uint64_t>(tile, n_t - uint64_t(tl) * tile));
+                items.push_back({bytes * per_byte, BItem{uint32_t(t), tl, g0, g1}});
+            }
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const ItemCost &a, const ItemCost &c) { return a.cost > c.cost; });
+    H.items.resize(items.size());
+    for (size_t i = 0; i < items.size(); ++i) H.items[i] = items[i].it;
+}
+
+hc_status batch_check(const BatchHost &H, const BatchDev &D) {
+    const size_t np = H.pats.size(), nv = H.views.size(), n_pairs = H.pair_base.size() - 1;
+    if (H.pair_base.empty() || H.glist.size() % 2) return HC_EINVAL;
+    const uint64_t x_bytes = lds_layout(D.tile, D.max_m, D.table_bytes, 0).x_bytes;
+    std::vector<uint8_t> seen(np, 0);
+    for (size_t g = 0; g < H.glist.size(); g += 2) {
+        const uint32_t p = H.glist[g], k = H.glist[g + 1];
+        if (p >= np || k >= n_pairs) return HC_EINVAL;
+        if (seen[p]) continue;
+        seen[p] = 1;
+        const BPat &b = H.pats[p];
+        if (b.m < 1 || b.m > D.max_m || b.q < 1 || b.q > uint32_t(kMaxQ) || b.q > b.m) return HC_EINVAL;
+        if ((uint64_t(p) + 1) * D.table_bytes > D.Fs_bytes) return HC_EINVAL;
+        if (b.x_off % 16u || uint64_t(b.x_off) + x_bytes > D.xs_bytes) return HC_EINVAL;
+    }
+    for (const BItem &it : H.items) {
+        if (it.text >= nv || it.g0 >= it.g1 || uint64_t(it.g1) * 2 > H.glist.size()) return HC_EINVAL;
+        const TextView &v = H.views[it.text];
+        if (!v.ptr || uint64_t(it.tile) * D.tile >= std::min(v.len, v.start_limit)) return HC_EINVAL;
+        for (uint32_t g = it.g0; g < it.g1; ++g)
+            if (H.glist[2 * g + 1] >= n_pairs) return HC_EINVAL;
+        // the group's first pattern is its longest (its halo is staged)
+        for (uint32_t g = it.g0 + 1; g < it.g1; ++g)
+            if (H.pats[H.glist[2 * g]].m > H.pats[H.glist[2 * it.g0]].m) return HC_EINVAL;
+    }
+    return HC_OK;
+}
+
+hc_status batch_upload(const BatchHost &H, BatchDev &D, hipStream_t s) {
+    hc_status st = batch_check(H, D);
+    if (st != HC_OK) return st;
+    D.n_pairs = uint32_t(H.pair_base.size() - 1);
+    D.n_items = uint32_t(H.items.size());
+    D.n_entries = H.pair_base.back();
+    if ((st = D.views.upload(H.views.data(), H.views.size() * sizeof(TextView), s)) != HC_OK) return st;
+    if ((st = D.pats.upload(H.pats.data(), H.pats.size() * sizeof(BPat), s)) != HC_OK) return st;
+    if ((st = D.items.upload(H.items.data(), H.items.size() * sizeof(BItem), s)) != HC_OK) return st;
+    if ((st = D.glist.upload(H.glist.data(), H.glist.size() * 4, s)) != HC_OK) return st;
+    if ((st = D.pair_base.upload(H.pair_base.data(), H.pair_base.size() * 8, s)) != HC_OK) return st;
+    if (D.counts.ensure(D.n_entries * 4) != HC_OK || D.toff.ensure(D.n_entries * 4) != HC_OK ||
+        D.ctl.ensure(64) != HC_OK || D.tot.ensure(size_t(D.n_pairs) * 8) != HC_OK || D.grand.ensure(8) != HC_OK)
+        return HC_ENOMEM;
+    D.nb = uint32_t((uint64_t(D.n_pairs) + kScanBlock - 1) / kScanBlock);
+    if (D.bsum.ensure(size_t(std::max<uint32_t>(D.nb, 1)) * 8) != HC_OK) return HC_ENOMEM;
+    if (D.scratch_cap == 0) D.scratch_cap = 1u << 23;   // positions; grown when a run needs more
+    if (D.temp.ensure(D.scratch_cap * 8) != HC_OK) return HC_ENOMEM;
+    D.grid = std::max<uint32_t>(1, std::min<uint32_t>(D.n_items, D.max_grid));
+    return HC_OK;
+}
+
+hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pair_off, hipStream_t s) {
+    // every buffer the kernels read must be in place
+    if (D.n_items > 0 && (!D.Fs || !D.xs || !D.views.p || !D.pats.p || !D.items.p || !D.glist.p))
+        return HC_EINVAL;
+    if (!D.ctl.p || !D.pair_base.p || !D.temp.p || (D.n_pairs > 0 && (!D.tot.p || !D.counts.p || !D.toff.p)))
+        return HC_EINVAL;
+    hipLaunchKernelGGL(hc_batch_reset, dim3(1), dim3(64), 0, s, D.ctl.as<unsigned long long>());
     BatchArgs A;
-    A.text = P->d_text;
-    A.text_off = P->text_off.as<uint64_t>();
-    A.pats = P->pats.as<BPat>();
-    A.xs = P->xs.as<uint8_t>();
-    A.Fs = P->Fs.as<uint8_t>();
-    A.items = P->items.as<BItem>();
-    A.n_items = P->n_items;
-    A.glist = P->glist.as<uint32_t>();
-    A.pair_base = P->pair_base.as<uint64_t>();
-    A.counts = P->counts.as<uint32_t>();
-    A.toff = P->toff.as<uint32_t>();
-    A.temp = P->temp.as<int64_t>();
-    A.temp_cap = P->scratch_cap;
-    A.ctl = P->ctl.as<unsigned long long>();
-    A.tile = P->tile;
-    A.seg = P->seg;
-    A.table_bytes = P->table_bytes;
-    A.max_m = P->max_m;
-    if (P->n_items > 0) {
-        if (P->w == 16)
-            hipLaunchKernelGGL(hc_batch_kernel<uint16_t>, dim3(P->grid), dim3(kThreads), P->lds, s, A);
+    A.texts = D.views.as<TextView>();
+    A.pats = D.pats.as<BPat>();
+    A.xs = D.xs;
+    A.Fs = D.Fs;
+    A.items = D.items.as<BItem>();
+    A.n_items = D.n_items;
+    A.glist = D.glist.as<uint32_t>();
+    A.pair_base = D.pair_base.as<uint64_t>();
+    A.counts = D.counts.as<uint32_t>();
+    A.toff = D.toff.as<uint32_t>();
+    A.temp = D.temp.as<int64_t>();
+    A.temp_cap = D.scratch_cap;
+    A.ctl = D.ctl.as<unsigned long long>();
+    A.tile = D.tile;
+    A.seg = D.seg;
+    A.table_bytes = D.table_bytes;
+    A.max_m = D.max_m;
+    if (D.n_items > 0) {
+        if (D.w == 16)
+            hipLaunchKernelGGL(hc_batch_kernel<uint16_t>, dim3(D.grid), dim3(kThreads), D.lds, s, A);
         else
-            hipLaunchKernelGGL(hc_batch_kernel<uint32_t>, dim3(P->grid), dim3(kThreads), P->lds, s, A);
+            hipLaunchKernelGGL(hc_batch_kernel<uint32_t>, dim3(D.grid), dim3(kThreads), D.lds, s, A);
     }
-    const uint32_t pgrid = uint32_t((uint64_t(P->n_pairs) * kWave + 255u) / 256u);
-    if (P->n_pairs > 0) {
-        hipLaunchKernelGGL(hc_pair_totals, dim3(pgrid), dim3(256), 0, s, P->pair_base.as<uint64_t>(),
-                           uint64_t(P->n_pairs), P->counts.as<uint32_t>(), P->tot.as<uint64_t>());
-        hipLaunchKernelGGL(hc_scan_reduce, dim3(P->nb), dim3(256), 0, s, P->tot.as<uint64_t>(),
-                           uint64_t(P->n_pairs), P->bsum.as<uint64_t>());
+    const uint32_t pgrid = uint32_t((uint64_t(D.n_pairs) * kWave + 255u) / 256u);
+    if (D.n_pairs > 0) {
+        hipLaunchKernelGGL(hc_pair_totals, dim3(pgrid), dim3(256), 0, s, D.pair_base.as<uint64_t>(),
+                           uint64_t(D.n_pairs), D.counts.as<uint32_t>(), D.tot.as<uint64_t>());
+        hipLaunchKernelGGL(hc_scan_reduce, dim3(D.nb), dim3(256), 0, s, D.tot.as<uint64_t>(),
+                           uint64_t(D.n_pairs), D.bsum.as<uint64_t>());
     }
-    hipLaunchKernelGGL(hc_scan_blocks, dim3(1), dim3(256), 0, s, P->bsum.as<uint64_t>(), P->nb,
-                       P->grand.as<uint64_t>());
-    if (P->n_pairs > 0) {
-        hipLaunchKernelGGL(hc_scan_apply, dim3(P->nb), dim3(256), 0, s, P->tot.as<uint64_t>(),
-                           uint64_t(P->n_pairs), P->bsum.as<uint64_t>(), d_pair_off);
-    }
-    hipLaunchKernelGGL(hc_scan_total, dim3(1), dim3(1), 0, s, P->grand.as<uint64_t>(),
-                       d_pair_off + P->n_pairs);
-    if (P->n_pairs > 0 && cap > 0) {
-        hipLaunchKernelGGL(hc_pair_emit, dim3(pgrid), dim3(256), 0, s, P->pair_base.as<uint64_t>(),
-                           uint64_t(P->n_pairs), P->counts.as<uint32_t>(), P->toff.as<uint32_t>(),
-                           P->temp.as<int64_t>(), d_pair_off, d_pos, cap,
-                           P->ctl.as<unsigned long long>());
-    }
+    hipLaunchKernelGGL(hc_scan_blocks, dim3(1), dim3(256), 0, s, D.bsum.as<uint64_t>(), D.nb,
+                       D.grand.as<uint64_t>());
+    if (D.n_pairs > 0)
+        hipLaunchKernelGGL(hc_scan_apply, dim3(D.nb), dim3(256), 0, s, D.tot.as<uint64_t>(), uint64_t(D.n_pairs),
+                           D.bsum.as<uint64_t>(), d_pair_off);
+    hipLaunchKernelGGL(hc_scan_total, dim3(1), dim3(1), 0, s, D.grand.as<uint64_t>(), d_pair_off + D.n_pairs);
+    if (D.n_pairs > 0 && cap > 0)
+        hipLaunchKernelGGL(hc_pair_emit, dim3(pgrid), dim3(256), 0, s, D.pair_base.as<uint64_t>(),
+                           uint64_t(D.n_pairs), D.counts.as<uint32_t>(), D.toff.as<uint32_t>(),
+                           D.temp.as<int64_t>(), d_pair_off, d_pos, cap, D.ctl.as<unsigned long long>());
     return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
 }
 
+hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total) {
+    // every workgroup may leave at most one chunk partly unused
+    const uint64_t need = std::max<uint64_t>(reserved, total + uint64_t(D.grid + 16u) * kChunk);
+    if (D.temp.ensure(need * 8) != HC_OK) return HC_ENOMEM;
+    D.scratch_cap = need;
+    return HC_OK;
+}
+
 }  // namespace hc
+
+using namespace hc;
+
+struct hc_batch_plan {
+    BatchDev D;
+    DeviceBuf Fpool, xpool;
+    // graph for (d_pos, cap, d_pair_off, stream)
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int64_t *g_pos = nullptr, *g_off = nullptr;
+    int64_t g_cap = -1;
+    hipStream_t g_stream = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~hc_batch_plan() { drop_graph(); }
+};
 
 extern "C" {
 
@@ -512,176 +685,67 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
                            !b->d_text))
         return HC_EINVAL;
     if (b->n_pairs > int64_t(0x7FFFFFFF)) return HC_EINVAL;
-    const DeviceInfo &di = device_info();
-    if (!di.ok) return HC_EHIP;
-    std::unique_ptr<hc_batch_plan> P(new (std::nothrow) hc_batch_plan());
-    if (!P) return HC_ENOMEM;
-    P->device = di.device;
-    P->d_text = b->d_text;
-    P->n_pairs = uint32_t(b->n_pairs);
+    if (!device_info().ok) return HC_EHIP;
     for (int32_t t = 0; t < b->n_texts; ++t) {
         if (b->text_off[t + 1] < b->text_off[t]) return HC_EINVAL;
         if (b->text_off[t + 1] - b->text_off[t] > int64_t(0xFFFFFFFFll)) return HC_EINVAL;
     }
-    for (int32_t i = 0; i < b->n_pats; ++i)
-        if (b->pat_off[i + 1] - b->pat_off[i] < 1 || b->pat_off[i + 1] - b->pat_off[i] > kMaxM)
-            return HC_EINVAL;
     for (int64_t k = 0; k < b->n_pairs; ++k)
         if (b->pair_pat[k] < 0 || b->pair_pat[k] >= b->n_pats || b->pair_text[k] < 0 ||
             b->pair_text[k] >= b->n_texts)
             return HC_EINVAL;
-
-    // common table shape for the batch; q per pattern
-    int w = params && params->w ? params->w : 16;
-    int alpha = params && params->alpha ? params->alpha : 12;
-    if ((w != 16 && w != 32) || alpha < 1 || alpha > alpha_max(w)) return HC_EINVAL;
-    P->w = uint32_t(w);
-    P->table_bytes = uint32_t((size_t(1) << alpha) * size_t(w / 8));
-    P->table_bytes = std::max<uint32_t>(16, (P->table_bytes + 15u) & ~15u);
-    if (P->table_bytes > uint32_t(kFStage) * kThreads * 16u) return HC_EINVAL;   // <= 16 KiB
-
-    const int32_t np = b->n_pats;
-    std::vector<BPat> bp(size_t(std::max(np, 1)));
-    std::vector<uint8_t> Fh(size_t(np) * P->table_bytes, 0);
-    std::vector<uint32_t> xoff(size_t(np) + 1, 0);
-    for (int32_t i = 0; i < np; ++i) {
-        const int64_t m = b->pat_off[i + 1] - b->pat_off[i];
-        xoff[i + 1] = xoff[i] + uint32_t(((m + 15) & ~int64_t(15)) + 32);
-    }
-    int64_t mmax = 1;
-    for (int32_t i = 0; i < np; ++i) mmax = std::max<int64_t>(mmax, b->pat_off[i + 1] - b->pat_off[i]);
-    // every pattern's bytes are read as a block of the longest pattern's size
-    std::vector<uint8_t> Xh(xoff[np] + size_t((mmax + 15) & ~int64_t(15)) + 64, 0);
-    for (int32_t i = 0; i < np; ++i) {
-        const uint8_t *x = b->pat + b->pat_off[i];
-        const int64_t m = b->pat_off[i + 1] - b->pat_off[i];
-        int q = params ? params->q : 0, a = alpha, ww = w;
-        default_params(m, distinct_bytes(x, m), q, a, ww);
-        q = int(std::min<int64_t>(q, m));
-        if (validate_params(m, q, alpha, w) != HC_OK) return HC_EINVAL;
-        PatternData pd;
-        build_link_table(x, m, q, alpha, w, pd);
-        std::vector<uint8_t> packed = pack_table(pd);
-        std::memcpy(Fh.data() + size_t(i) * P->table_bytes, packed.data(), packed.size());
-        std::memcpy(Xh.data() + xoff[i], x, size_t(m));
-        bp[i] = BPat{uint32_t(m), uint32_t(q), uint32_t(pd.s), pd.mask, pd.hv, xoff[i], 0, 0};
-        P->max_m = std::max<uint32_t>(P->max_m, uint32_t(m));
-    }
-
-    // tiles: as large as LDS allows, 4 workgroups per compute unit if possible
-    P->seg = 100;
-    P->tile = kThreads * P->seg;
-    LdsLayout L = lds_layout(P->tile, P->max_m, P->table_bytes, 0);
-    while ((L.total > di.max_lds_per_block || P->tile + P->max_m - 1u > stage_limit(kThreads)) &&
-           P->seg > 8) {
-        P->seg -= 4;
-        P->tile = kThreads * P->seg;
-        L = lds_layout(P->tile, P->max_m, P->table_bytes, 0);
-    }
-    if (L.total > di.max_lds_per_block) return HC_EINVAL;
-    P->lds = L.total;
-
-    // pairs grouped by text, longest pattern first, in groups of up to 128
-    const int32_t nt = b->n_texts;
-    std::vector<uint64_t> toff(size_t(nt) + 1, 0);
-    for (int32_t t = 0; t <= nt; ++t) toff[t] = uint64_t(b->text_off[t]);
-    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> by_text(size_t(std::max(nt, 1)));
-    std::vector<uint64_t> pair_base(size_t(P->n_pairs) + 1, 0);
-    for (uint32_t k = 0; k < P->n_pairs; ++k) {
-        const uint32_t p = uint32_t(b->pair_pat[k]), t = uint32_t(b->pair_text[k]);
-        by_text[t].push_back({p, k});
-        const uint64_t n_t = toff[t + 1] - toff[t], m = bp[p].m;
-        const uint64_t starts = n_t >= m ? n_t - m + 1 : 0;
-        pair_base[k + 1] = pair_base[k] + (starts + P->tile - 1) / P->tile;
-    }
-    P->n_entries = pair_base[P->n_pairs];
-    constexpr uint32_t kGroup = 128;
-    std::vector<uint32_t> glist;
-    struct ItemCost {
-        double cost;
-        BItem it;
-    };
-    std::vector<ItemCost> items;
-    for (int32_t t = 0; t < nt; ++t) {
-        auto &v = by_text[t];
-        std::sort(v.begin(), v.end(), [&](const std::pair<uint32_t, uint32_t> &a,
-                                          const std::pair<uint32_t, uint32_t> &c) {
-            return bp[a.first].m > bp[c.first].m || (bp[a.first].m == bp[c.first].m && a.second < c.second);
-        });
-        const uint64_t n_t = toff[t + 1] - toff[t];
-        const uint32_t tiles = uint32_t((n_t + P->tile - 1) / P->tile);
-        for (size_t g = 0; g < v.size(); g += kGroup) {
-            const uint32_t g0 = uint32_t(glist.size() / 2);
-            double per_byte = 0;
-            for (size_t j = g; j < std::min(v.size(), g + kGroup); ++j) {
-                glist.push_back(v[j].first);
-                glist.push_back(v[j].second);
-                const BPat &q = bp[v[j].first];
-                per_byte += 1.0 / double(q.m - q.q + 1) + 0.02;
-            }
-            const uint32_t g1 = uint32_t(glist.size() / 2);
-            for (uint32_t tl = 0; tl < tiles; ++tl) {
-                const double bytes = double(std::min<uint64_t>(P->tile, n_t - uint64_t(tl) * P->tile));
-                items.push_back({bytes * per_byte, BItem{uint32_t(t), tl, g0, g1}});
-            }
-        }
-    }
-    std::stable_sort(items.begin(), items.end(),
-                     [](const ItemCost &a, const ItemCost &c) { return a.cost > c.cost; });
-    std::vector<BItem> ih(items.size());
-    for (size_t i = 0; i < items.size(); ++i) ih[i] = items[i].it;
-    P->n_items = uint32_t(ih.size());
-
-    // device buffers
-    auto up = [&](DeviceBuf &d, const void *src, size_t bytes) -> hc_status {
-        if (d.ensure(bytes) != HC_OK) return HC_ENOMEM;
-        if (bytes && hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return HC_EHIP;
-        return HC_OK;
-    };
-    hc_status st;
-    if ((st = up(P->text_off, toff.data(), toff.size() * 8)) != HC_OK) return st;
-    if ((st = up(P->pats, bp.data(), bp.size() * sizeof(BPat))) != HC_OK) return st;
-    if ((st = up(P->xs, Xh.data(), Xh.size())) != HC_OK) return st;
-    if ((st = up(P->Fs, Fh.data(), std::max<size_t>(Fh.size(), 16))) != HC_OK) return st;
-    if ((st = up(P->items, ih.data(), ih.size() * sizeof(BItem))) != HC_OK) return st;
-    if ((st = up(P->glist, glist.data(), glist.size() * 4)) != HC_OK) return st;
-    if ((st = up(P->pair_base, pair_base.data(), pair_base.size() * 8)) != HC_OK) return st;
-    if (P->counts.ensure(P->n_entries * 4) != HC_OK || P->toff.ensure(P->n_entries * 4) != HC_OK ||
-        P->ctl.ensure(64) != HC_OK || P->tot.ensure(size_t(P->n_pairs) * 8) != HC_OK ||
-        P->grand.ensure(8) != HC_OK)
-        return HC_ENOMEM;
-    P->nb = uint32_t((uint64_t(P->n_pairs) + kScanBlock - 1) / kScanBlock);
-    if (P->bsum.ensure(size_t(std::max<uint32_t>(P->nb, 1)) * 8) != HC_OK) return HC_ENOMEM;
-    P->scratch_cap = 1u << 23;   // positions; grown when a run needs more
-    if (P->temp.ensure(P->scratch_cap * 8) != HC_OK) return HC_ENOMEM;
-    int per_cu = 1;
-    st = P->w == 16 ? batch_occupancy<uint16_t>(P->lds, &per_cu) : batch_occupancy<uint32_t>(P->lds, &per_cu);
+    std::unique_ptr<hc_batch_plan> P(new (std::nothrow) hc_batch_plan());
+    if (!P) return HC_ENOMEM;
+    int alpha = 0, w = 0;
+    uint32_t table_bytes = 0;
+    hc_status st = batch_shape(params, alpha, w, table_bytes);
     if (st != HC_OK) return st;
-    P->grid = std::max<uint32_t>(1, std::min<uint32_t>(P->n_items, uint32_t(di.cus) * uint32_t(per_cu)));
+    // common table shape for the batch; q per pattern
+    BatchHost H;
+    std::vector<uint8_t> Fh, Xh;
+    uint32_t max_m = 1;
+    if ((st = pack_patterns(b->pat, b->pat_off, b->n_pats, params, alpha, w, table_bytes, H.pats, Fh, Xh,
+                            max_m)) != HC_OK)
+        return st;
+    if ((st = batch_geometry(P->D, max_m, table_bytes, uint32_t(w))) != HC_OK) return st;
+    H.views.resize(size_t(b->n_texts));
+    for (int32_t t = 0; t < b->n_texts; ++t) {
+        const uint64_t len = uint64_t(b->text_off[t + 1] - b->text_off[t]);
+        H.views[t] = TextView{b->d_text + b->text_off[t], len, len};
+    }
+    std::vector<std::pair<uint32_t, uint32_t>> pairs(size_t(b->n_pairs));
+    for (int64_t k = 0; k < b->n_pairs; ++k) pairs[k] = {uint32_t(b->pair_pat[k]), uint32_t(b->pair_text[k])};
+    batch_build(H, pairs, P->D.tile, kBatchGroup);
+    hipStream_t s = nullptr;
+    if ((st = P->Fpool.upload(Fh.data(), Fh.size(), s)) != HC_OK) return st;
+    if ((st = P->xpool.upload(Xh.data(), Xh.size(), s)) != HC_OK) return st;
+    P->D.Fs = P->Fpool.as<uint8_t>();
+    P->D.xs = P->xpool.as<uint8_t>();
+    P->D.Fs_bytes = P->Fpool.bytes;
+    P->D.xs_bytes = P->xpool.bytes;
+    if ((st = batch_upload(H, P->D, s)) != HC_OK) return st;
+    // the host vectors above go out of scope: wait for the copies
+    if (hipStreamSynchronize(s) != hipSuccess) return HC_EHIP;
     *out = P.release();
     return HC_OK;
 }
 
 void hc_batch_plan_free(hc_batch_plan *p) { delete p; }
 
-hc_status hc_batch_plan_run(hc_batch_plan *P, int64_t *d_pos, int64_t cap, int64_t *d_pair_off,
-                            int64_t *total, void *stream) {
+hc_status hc_batch_plan_run(hc_batch_plan *P, int64_t *d_pos, int64_t cap, int64_t *d_pair_off, int64_t *total,
+                            void *stream) {
     if (!P || !total || !d_pair_off || cap < 0 || (cap > 0 && !d_pos)) return HC_EINVAL;
     *total = 0;
     hipStream_t s = hipStream_t(stream);
     for (int attempt = 0; attempt < 2; ++attempt) {
         // (re)build the graph for these buffers
-        if (!P->exec || P->g_pos != d_pos || P->g_off != d_pair_off || P->g_cap != cap ||
-            P->g_stream != s) {
-            if (P->exec) (void)hipGraphExecDestroy(P->exec);
-            if (P->graph) (void)hipGraphDestroy(P->graph);
-            P->exec = nullptr;
-            P->graph = nullptr;
+        if (!P->exec || P->g_pos != d_pos || P->g_off != d_pair_off || P->g_cap != cap || P->g_stream != s) {
+            P->drop_graph();
             hipStream_t cs;
             if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return HC_EHIP;
             hc_status st = HC_OK;
             if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = HC_EHIP;
-            if (st == HC_OK) st = enqueue_batch(P, d_pos, cap, d_pair_off, cs);
+            if (st == HC_OK) st = batch_enqueue(P->D, d_pos, cap, d_pair_off, cs);
             hipGraph_t g = nullptr;
             if (hipStreamEndCapture(cs, &g) != hipSuccess && st == HC_OK) st = HC_EHIP;
             (void)hipStreamDestroy(cs);
@@ -702,21 +766,15 @@ hc_status hc_batch_plan_run(hc_batch_plan *P, int64_t *d_pos, int64_t cap, int64
         if (hipGraphLaunch(P->exec, s) != hipSuccess) return HC_EHIP;
         unsigned long long ctl[4] = {0, 0, 0, 0};
         int64_t tot = 0;
-        if (hipMemcpyAsync(ctl, P->ctl.p, sizeof(ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(&tot, d_pair_off + P->n_pairs, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (hipMemcpyAsync(ctl, P->D.ctl.p, sizeof(ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&tot, d_pair_off + P->D.n_pairs, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return HC_EHIP;
         *total = tot;
         if (ctl[2] == 0ull) return tot > cap ? HC_EOVERFLOW : HC_OK;
-        // scratch was too small: grow it to the reserved size and run again
-        // every workgroup may leave at most one chunk partly unused
-        const uint64_t need = std::max<uint64_t>(ctl[1], uint64_t(tot) + uint64_t(P->grid + 16u) * kChunk);
-        if (P->temp.ensure(need * 8) != HC_OK) return HC_ENOMEM;
-        P->scratch_cap = need;
-        if (P->exec) (void)hipGraphExecDestroy(P->exec);
-        if (P->graph) (void)hipGraphDestroy(P->graph);
-        P->exec = nullptr;
-        P->graph = nullptr;
+        // scratch was too small: grow it and run again
+        if (batch_grow_scratch(P->D, ctl[1], uint64_t(tot)) != HC_OK) return HC_ENOMEM;
+        P->drop_graph();
     }
     return HC_EHIP;
 }
