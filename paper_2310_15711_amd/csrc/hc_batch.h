@@ -58,6 +58,7 @@ struct BatchDev {
     const uint8_t *Fs = nullptr;   // table_bytes per pattern index
     const uint8_t *xs = nullptr;   // pattern bytes at BPat::x_off
     size_t Fs_bytes = 0, xs_bytes = 0;
+    hipError_t last_error = hipSuccess;   // of the last batch_enqueue
     DeviceBuf views, pats, items, glist, pair_base, counts, toff, temp, ctl, tot, bsum, grand;
 };
 

@@ -642,12 +642,17 @@ hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pai
         hipLaunchKernelGGL(hc_pair_emit, dim3(pgrid), dim3(256), 0, s, D.pair_base.as<uint64_t>(),
                            uint64_t(D.n_pairs), D.counts.as<uint32_t>(), D.toff.as<uint32_t>(),
                            D.temp.as<int64_t>(), d_pair_off, d_pos, cap, D.ctl.as<unsigned long long>());
-    return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
+    D.last_error = hipGetLastError();
+    return D.last_error == hipSuccess ? HC_OK : HC_EHIP;
 }
 
 hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total) {
-    // every workgroup may leave at most one chunk partly unused
-    const uint64_t need = std::max<uint64_t>(reserved, total + uint64_t(D.grid + 16u) * kChunk);
+    // A workgroup reserves a new chunk of max(kChunk, c) when the c positions
+    // of a (pair, tile) do not fit in what is left of its chunk; that rest
+    // (< c) is abandoned. So the abandoned rests sum to at most `total`, and
+    // every workgroup ends with at most one chunk partly used: a run never
+    // reserves more than 2 * total + grid * kChunk.
+    const uint64_t need = std::max<uint64_t>(reserved, 2 * total + uint64_t(D.grid + 16u) * kChunk);
     if (D.temp.ensure(need * 8) != HC_OK) return HC_ENOMEM;
     D.scratch_cap = need;
     return HC_OK;

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -156,6 +157,12 @@ struct hc_server {
 // One step: the current chunk of every text with active requests, for all
 // of them (`members`, in pair order); their positions are appended.
 hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64_t &bytes) {
+    auto fail = [&](const char *where, hc_status st) {
+        const hipError_t e = hipGetLastError();
+        std::fprintf(stderr, "hc_serve: step failed in %s: %s (HIP: %s; launch: %s)\n", where, hc_strerror(st),
+                     hipGetErrorString(e), hipGetErrorString(D.last_error));
+        return st;
+    };
     BatchHost H;
     std::vector<std::pair<uint32_t, uint32_t>> pairs;
     std::vector<int32_t> text_of_view;
@@ -192,36 +199,37 @@ hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64
     while (bucket < max_m) bucket *= 2;
     if (bucket != D.max_m || D.tile == 0) {
         hc_status st = batch_geometry(D, std::min<uint32_t>(bucket, uint32_t(kMaxM)), table_bytes, uint32_t(w));
-        if (st != HC_OK) return st;
+        if (st != HC_OK) return fail("geometry", st);
     }
     batch_build(H, pairs, D.tile, kBatchGroup);
     hc_status st = batch_upload(H, D, stream);
-    if (st != HC_OK) return st;
+    if (st != HC_OK) return fail("upload", st);
     const size_t np = pairs.size();
-    if (d_off.ensure((np + 1) * 8) != HC_OK || pinned(h_off, h_off_cap, np + 1) != HC_OK) return HC_ENOMEM;
+    if (d_off.ensure((np + 1) * 8) != HC_OK || pinned(h_off, h_off_cap, np + 1) != HC_OK)
+        return fail("offsets", HC_ENOMEM);
     int64_t cap = int64_t(np * kResultReserve);
     if (d_pos.bytes / 8 > size_t(cap)) cap = int64_t(d_pos.bytes / 8);
-    if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return HC_ENOMEM;
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        if ((st = batch_enqueue(D, d_pos.as<int64_t>(), cap, d_off.as<int64_t>(), stream)) != HC_OK) return st;
+    if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
+    // a second run, with room for everything the first one counted, always fits
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if ((st = batch_enqueue(D, d_pos.as<int64_t>(), cap, d_off.as<int64_t>(), stream)) != HC_OK)
+            return fail("launch", st);
         if (hipMemcpyAsync(h_ctl, D.ctl.p, 4 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipMemcpyAsync(h_off, d_off.p, (np + 1) * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
-            return HC_EHIP;
+            return fail("counts", HC_EHIP);
         const uint64_t total = uint64_t(h_off[np]);
-        if (h_ctl[2] != 0ull) {   // scratch too small
-            if (batch_grow_scratch(D, h_ctl[1], total) != HC_OK) return HC_ENOMEM;
-            continue;
-        }
-        if (total > uint64_t(cap)) {   // more positions than reserved: room for all, then again
+        const bool short_scratch = h_ctl[2] != 0ull, short_out = total > uint64_t(cap);
+        if (short_scratch && batch_grow_scratch(D, h_ctl[1], total) != HC_OK) return fail("scratch", HC_ENOMEM);
+        if (short_out) {
             cap = int64_t(total);
-            if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return HC_ENOMEM;
-            continue;
+            if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
         }
-        if (pinned(h_pos, h_pos_cap, total) != HC_OK) return HC_ENOMEM;
+        if (short_scratch || short_out) continue;
+        if (pinned(h_pos, h_pos_cap, total) != HC_OK) return fail("host positions", HC_ENOMEM);
         if (total && (hipMemcpyAsync(h_pos, d_pos.p, total * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
                       hipStreamSynchronize(stream) != hipSuccess))
-            return HC_EHIP;
+            return fail("positions copy", HC_EHIP);
         std::vector<int32_t> view_of_text(texts.size(), -1);
         for (size_t v = 0; v < text_of_view.size(); ++v) view_of_text[text_of_view[v]] = int32_t(v);
         bytes = 0;
@@ -234,11 +242,12 @@ hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64
         }
         return HC_OK;
     }
-    return HC_EHIP;
+    return fail("retry", HC_EHIP);
 }
 
 void hc_server::run() {
     if (hipSetDevice(device) != hipSuccess) {
+        std::fprintf(stderr, "hc_serve: hipSetDevice(%d) failed\n", device);
         std::lock_guard<std::mutex> g(mu);
         fatal = HC_EHIP;
         cv_done.notify_all();
@@ -267,8 +276,10 @@ void hc_server::run() {
             if (hipMemcpyAsync(Fpool.as<uint8_t>() + size_t(r->slot) * table_bytes, r->F.data(), table_bytes,
                                hipMemcpyHostToDevice, stream) != hipSuccess ||
                 hipMemcpyAsync(xpool.as<uint8_t>() + size_t(r->slot) * kXStride, r->x.data(), r->x.size(),
-                               hipMemcpyHostToDevice, stream) != hipSuccess)
+                               hipMemcpyHostToDevice, stream) != hipSuccess) {
+                std::fprintf(stderr, "hc_serve: pattern upload failed: %s\n", hipGetErrorString(hipGetLastError()));
                 st = HC_EHIP;
+            }
         }
         uint64_t bytes = 0;
         if (st == HC_OK) st = step(members, bytes);
