@@ -224,6 +224,10 @@ hc_status hc_serve_submit(hc_server *s, int32_t text_id, const uint8_t *x,
                           int64_t m, uint64_t *req_id);
 hc_status hc_serve_poll(hc_server *s, uint64_t req_id, int64_t *out, int64_t cap,
                         int64_t *count, int32_t timeout_us);
+/* hc_serve_next_done waits up to timeout_us for a completed request that
+ * has not been reported yet and not been released, and returns its id (each
+ * id once, in completion order); HC_EAGAIN when none completed in time. */
+hc_status hc_serve_next_done(hc_server *s, uint64_t *req_id, int32_t timeout_us);
 hc_status hc_serve_stats(hc_server *s, double *p50_us, double *p99_us,
                          double *agg_gbps, int64_t *done);
 hc_status hc_serve_destroy(hc_server *s);

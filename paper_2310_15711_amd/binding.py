@@ -25,7 +25,7 @@ HC_VARIANT_AUTO, HC_VARIANT_HC, HC_VARIANT_SENTINEL, HC_VARIANT_SPARSE = 0, 1, 2
 EXPORTED = (
     "hc_preprocess", "hc_pattern_info", "hc_pattern_free", "hc_search", "hc_search_async",
     "hc_search_batched", "hc_batch_plan_create", "hc_batch_plan_run", "hc_batch_plan_free",
-    "hc_serve_create", "hc_serve_submit", "hc_serve_poll",
+    "hc_serve_create", "hc_serve_submit", "hc_serve_poll", "hc_serve_next_done",
     "hc_serve_stats", "hc_serve_destroy", "hc_strerror",
 )
 
@@ -79,6 +79,7 @@ def lib():
         "hc_serve_create": (i32, [p, p, i32, i64, p, P(p)]),
         "hc_serve_submit": (i32, [p, i32, p, i64, P(u64)]),
         "hc_serve_poll": (i32, [p, u64, p, i64, P(i64), i32]),
+        "hc_serve_next_done": (i32, [p, P(u64), i32]),
         "hc_serve_stats": (i32, [p, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double), P(i64)]),
         "hc_serve_destroy": (i32, [p]),
         "hc_strerror": (ctypes.c_char_p, [i32]),
@@ -328,6 +329,15 @@ class Server:
                 continue
             if time.monotonic() > end:
                 raise TimeoutError(f"request {req_id} not done after {timeout_s} s")
+
+    def next_done(self, timeout_us: int = 0):
+        """Id of a request that completed and was not reported yet, or None."""
+        rid = ctypes.c_uint64()
+        st = lib().hc_serve_next_done(self.handle, ctypes.byref(rid), int(timeout_us))
+        if st == HC_EAGAIN:
+            return None
+        _check(st, "hc_serve_next_done")
+        return rid.value
 
     def stats(self) -> dict:
         p50, p99, gbps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

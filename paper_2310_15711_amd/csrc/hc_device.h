@@ -496,6 +496,9 @@ __device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t
                 if ((pk.owner & 1u) == 0u) J0 = pk.J; else J1 = pk.J;
                 myslot = kParkCap;
             }
+            // slots are numbered from 0 again in the next round: every wave
+            // must have read its walk's result before any wave parks again
+            lds_barrier();
         }
     }
     const bool has = *any != 0u;

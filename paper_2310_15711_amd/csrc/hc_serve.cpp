@@ -95,6 +95,7 @@ struct hc_server {
     std::deque<std::shared_ptr<Request>> pending;
     std::vector<std::shared_ptr<Request>> active;   // by slot (null = free)
     std::unordered_map<uint64_t, std::shared_ptr<Request>> by_id;
+    std::deque<uint64_t> done_q;   // completed ids not yet taken by hc_serve_next_done
     uint64_t used_bytes = 0;
     std::vector<double> lat_us;
     double busy_s = 0, bytes_searched = 0;
@@ -129,6 +130,7 @@ struct hc_server {
             if (t.n < r->x.size()) {   // no window fits: complete at once
                 pending.pop_front();
                 r->done = true;
+                done_q.push_back(r->id);
                 lat_us.push_back(std::chrono::duration<double, std::micro>(Clock::now() - r->t_submit).count());
                 continue;
             }
@@ -225,7 +227,12 @@ hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64
             cap = int64_t(total);
             if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
         }
-        if (short_scratch || short_out) continue;
+        if (short_scratch || short_out) {
+            if (attempt == 1)
+                std::fprintf(stderr, "hc_serve: second run short (scratch %d, out %d, total %llu, cap %lld)\n",
+                             int(short_scratch), int(short_out), (unsigned long long)total, (long long)cap);
+            continue;
+        }
         if (pinned(h_pos, h_pos_cap, total) != HC_OK) return fail("host positions", HC_ENOMEM);
         if (total && (hipMemcpyAsync(h_pos, d_pos.p, total * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
                       hipStreamSynchronize(stream) != hipSuccess))
@@ -310,6 +317,7 @@ void hc_server::run() {
                 if (r->wrapped)
                     std::rotate(r->pos.begin(), r->pos.begin() + ptrdiff_t(r->wrap_at), r->pos.end());
                 r->done = true;
+                done_q.push_back(r->id);
                 active[r->slot] = nullptr;
                 used_bytes -= per_request;
                 lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
@@ -416,6 +424,29 @@ hc_status hc_serve_poll(hc_server *s, uint64_t req_id, int64_t *out, int64_t cap
     if (cap > 0) std::memcpy(out, r->pos.data(), size_t(std::min(c, cap)) * 8);
     if (c > cap) return HC_EOVERFLOW;   // kept: poll again with room for all
     s->by_id.erase(it);
+    if (s->done_q.size() > 2 * s->by_id.size() + 1024) {   // drop released ids
+        std::deque<uint64_t> keep;
+        for (uint64_t id : s->done_q)
+            if (s->by_id.count(id)) keep.push_back(id);
+        s->done_q.swap(keep);
+    }
+    return HC_OK;
+}
+
+hc_status hc_serve_next_done(hc_server *s, uint64_t *req_id, int32_t timeout_us) {
+    if (!s || !req_id) return HC_EINVAL;
+    *req_id = 0;
+    std::unique_lock<std::mutex> g(s->mu);
+    auto ready = [&] {
+        // ids already released by hc_serve_poll are skipped
+        while (!s->done_q.empty() && !s->by_id.count(s->done_q.front())) s->done_q.pop_front();
+        return !s->done_q.empty() || s->fatal != HC_OK;
+    };
+    if (!ready() && timeout_us > 0)
+        s->cv_done.wait_for(g, std::chrono::microseconds(timeout_us), ready);
+    if (s->done_q.empty()) return s->fatal != HC_OK ? s->fatal : HC_EAGAIN;
+    *req_id = s->done_q.front();
+    s->done_q.pop_front();
     return HC_OK;
 }
 

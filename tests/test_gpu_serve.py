@@ -193,3 +193,23 @@ def test_concurrent_submitters(texts):
     srv.close()
     assert not errors, errors
     check(host, reqs, got)
+
+
+def test_completion_queue_reports_each_request_once(texts):
+    host, dev = texts
+    srv = B.Server(dev, 128 * MiB)
+    try:
+        reqs = requests(host, 50, 5) + [(3, b"ACGTAC")]   # the last one completes at admission
+        announce("serve next_done", len(reqs))
+        ids = [srv.submit(t, x) for t, x in reqs]
+        seen = []
+        while len(seen) < len(ids):
+            rid = srv.next_done(timeout_us=2_000_000)
+            assert rid is not None, "a request did not complete"
+            seen.append(rid)
+        assert sorted(seen) == sorted(ids)
+        assert srv.next_done() is None
+        got = [srv.result(i) for i in ids]
+    finally:
+        srv.close()
+    check(host, reqs, got)
