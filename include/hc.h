@@ -63,8 +63,13 @@ typedef struct {
  *             only skips windows that cannot match, Section 3.3);
  *   wave      the 64 lanes of a wavefront try 64 consecutive windows and the
  *             wavefront moves on to the furthest position any lane proved
- *             safe (shift agreement across the wavefront). */
-enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2 };
+ *             safe (shift agreement across the wavefront);
+ *   dense     every window of the text gets the test the search loop applies
+ *             (first word, then the chain of links back to the window start,
+ *             then H_v), one window per lane, no shifts; the surviving
+ *             windows are verified. For short shifts (m - q + 1 small), where
+ *             the loop saves little, this avoids its divergence. */
+enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENSE = 3 };
 
 /* Searching-phase variant (no effect on results).
  *   hc        the plain searching phase (Section 3.3);
@@ -86,6 +91,33 @@ typedef struct {
 } hc_launch;
 
 typedef struct hc_pattern hc_pattern;   /* opaque; immutable once built      */
+
+/*
+ * hc_autotune -- measure the fastest parameters for each pattern length in
+ * ms[0..n_ms) on the device text d_y[0..n) (n <= 4 GiB, 1 <= m <= min(n,
+ * 4096)), and make them the library's choice for fields left at 0 (hc_params
+ * of hc_preprocess and batch plans, segment and schedule of hc_launch) for
+ * every pattern whose length falls in the same bucket (2^(b-1), 2^b]; the
+ * last tuning of a bucket wins, process-wide. Candidates: q in [1, min(m,
+ * 8)], (alpha, w) in {(8,8), (10,16), (11,16), (12,16), (12,32)}, the segment
+ * and dense schedules, segments {64, 100, 132, 200}; timed with `patterns`
+ * (1..64) patterns copied from the text at fixed pseudo-random offsets.
+ * out[i] (may be NULL) receives the choice for ms[i] and its median text
+ * GB/s. Runs on `stream` and synchronises it; allocates a scratch output of
+ * min(n, 2^25) positions. The choice never changes search results (the
+ * parameters only change speed). Errors: HC_EINVAL on bad arguments.
+ * hc_autotune_reset forgets every tuned entry.
+ */
+typedef struct {
+    int64_t m;
+    hc_params params;
+    hc_launch launch;
+    double gbps;
+} hc_tuning;
+
+hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *ms, int32_t n_ms,
+                      int32_t patterns, hc_tuning *out, void *stream);
+void hc_autotune_reset(void);
 
 /*
  * hc_preprocess -- the preprocessing phase (Section 3.1, eqs. (1)-(2);

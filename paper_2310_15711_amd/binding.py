@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhc.so")
 
 HC_OK, HC_EINVAL, HC_ENOMEM, HC_EOVERFLOW, HC_EAGAIN, HC_EHIP = 0, -1, -2, -3, -4, -5
-HC_SCHED_AUTO, HC_SCHED_SEGMENT, HC_SCHED_WAVE = 0, 1, 2
+HC_SCHED_AUTO, HC_SCHED_SEGMENT, HC_SCHED_WAVE, HC_SCHED_DENSE = 0, 1, 2, 3
 HC_VARIANT_AUTO, HC_VARIANT_HC, HC_VARIANT_SENTINEL, HC_VARIANT_SPARSE = 0, 1, 2, 3
 
 # every symbol declared in include/hc.h
@@ -26,7 +26,7 @@ EXPORTED = (
     "hc_preprocess", "hc_pattern_info", "hc_pattern_free", "hc_search", "hc_search_async",
     "hc_search_batched", "hc_batch_plan_create", "hc_batch_plan_run", "hc_batch_plan_free",
     "hc_serve_create", "hc_serve_submit", "hc_serve_poll", "hc_serve_next_done",
-    "hc_serve_stats", "hc_serve_destroy", "hc_strerror",
+    "hc_serve_stats", "hc_serve_destroy", "hc_strerror", "hc_autotune", "hc_autotune_reset",
 )
 
 
@@ -43,6 +43,11 @@ class hc_params(ctypes.Structure):
 class hc_launch(ctypes.Structure):
     _fields_ = [("segment", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+
+class hc_tuning(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("params", hc_params), ("launch", hc_launch),
+                ("gbps", ctypes.c_double)]
 
 
 class hc_batch(ctypes.Structure):
@@ -83,6 +88,8 @@ def lib():
         "hc_serve_stats": (i32, [p, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double), P(i64)]),
         "hc_serve_destroy": (i32, [p]),
         "hc_strerror": (ctypes.c_char_p, [i32]),
+        "hc_autotune": (i32, [p, i64, P(i64), i32, i32, p, p]),
+        "hc_autotune_reset": (None, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -356,3 +363,19 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def hc_autotune(y_dev, lengths, patterns: int = 5, stream=None) -> list:
+    """Tunes q, alpha, w, schedule and segment per pattern length on a device
+    text and installs the choices as defaults; returns them as dicts."""
+    ms = (ctypes.c_int64 * len(lengths))(*[int(m) for m in lengths])
+    out = (hc_tuning * len(lengths))()
+    _check(lib().hc_autotune(_dev_ptr(y_dev, "torch.uint8"), int(y_dev.numel()), ms, len(lengths),
+                             int(patterns), out, _stream_ptr(stream)), "hc_autotune")
+    return [{"m": t.m, "params": (t.params.q, t.params.alpha, t.params.w),
+             "launch": (t.launch.segment, t.launch.schedule, t.launch.variant, t.launch.wg_per_cu),
+             "gbps": t.gbps} for t in out]
+
+
+def hc_autotune_reset() -> None:
+    lib().hc_autotune_reset()

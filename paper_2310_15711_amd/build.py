@@ -30,6 +30,7 @@ SOURCES = [
     "hc_search.hip",
     "hc_batched.hip",
     "hc_serve.cpp",
+    "hc_autotune.cpp",
 ]
 
 

@@ -1,0 +1,167 @@
+// Autotuner: measures, on the caller's device text, which parameters (q,
+// alpha, w) and launch shape (schedule, segment) make the searching phase
+// fastest for each requested pattern length, and installs the winners as the
+// library's defaults for that length bucket.
+//
+// For each length m, sample patterns are copied out of the text at fixed
+// pseudo-random offsets (so they occur at least once, like the paper's
+// randomly extracted patterns, Section 4). Phase 1 times every (q, alpha, w,
+// schedule) candidate on two patterns at the default segment; phase 2 times
+// the four best with several segments on all sample patterns. The median
+// time per launch decides. Results never depend on the choice, only speed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "hc_internal.h"
+#include "hc_runtime.h"
+
+namespace hc {
+namespace {
+
+struct Cand {
+    int q, alpha, w, schedule, segment;
+    double ms = 0;
+};
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Median milliseconds per launch of one candidate over `pats`.
+hc_status time_candidate(const Cand &c, const std::vector<std::vector<uint8_t>> &pats, size_t np,
+                         const uint8_t *d_y, int64_t n, int64_t *d_out, int64_t cap, int64_t *d_count,
+                         hipStream_t s, double *ms) {
+    std::vector<hc_pattern *> hs;
+    hc_status st = HC_OK;
+    for (size_t i = 0; i < np && st == HC_OK; ++i) {
+        hc_params prm{c.q, c.alpha, c.w};
+        hc_pattern *p = nullptr;
+        st = hc_preprocess(pats[i].data(), int64_t(pats[i].size()), &prm, &p);
+        if (st == HC_OK) hs.push_back(p);
+    }
+    const hc_launch lc{c.segment, c.schedule, HC_VARIANT_HC, 0};
+    std::vector<Timer> ev(hs.size());
+    if (st == HC_OK && !hs.empty())   // warm-up: uploads the table, loads the kernel
+        st = hc_search_async(hs[0], d_y, n, d_out, cap, d_count, &lc, s);
+    for (size_t i = 0; i < hs.size() && st == HC_OK; ++i) {
+        if (hipEventCreate(&ev[i].a) != hipSuccess || hipEventCreate(&ev[i].b) != hipSuccess ||
+            hipEventRecord(ev[i].a, s) != hipSuccess) {
+            st = HC_EHIP;
+            break;
+        }
+        st = hc_search_async(hs[i], d_y, n, d_out, cap, d_count, &lc, s);
+        if (st == HC_OK && hipEventRecord(ev[i].b, s) != hipSuccess) st = HC_EHIP;
+    }
+    if (st == HC_OK && hipStreamSynchronize(s) != hipSuccess) st = HC_EHIP;
+    std::vector<double> t;
+    for (size_t i = 0; i < hs.size() && st == HC_OK; ++i) {
+        float f = 0;
+        if (hipEventElapsedTime(&f, ev[i].a, ev[i].b) != hipSuccess) st = HC_EHIP;
+        t.push_back(f);
+    }
+    for (hc_pattern *p : hs) hc_pattern_free(p);
+    if (st != HC_OK) return st;
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    *ms = t[t.size() / 2];
+    return HC_OK;
+}
+
+std::vector<Cand> candidates(int64_t m) {
+    static const int shapes[][2] = {{8, 8}, {10, 16}, {11, 16}, {12, 16}, {12, 32}};
+    std::vector<Cand> out;
+    for (int q = 1; q <= std::min<int64_t>(kMaxQ, m); ++q)
+        for (const auto &aw : shapes) {
+            if (aw[0] > alpha_max(aw[1])) continue;
+            out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, 100});
+            if (q <= 4 && m / q - 1 <= 3) out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_DENSE, 100});
+        }
+    return out;
+}
+
+}  // namespace
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *ms, int32_t n_ms,
+                                 int32_t patterns, hc_tuning *out, void *stream) {
+    if (!d_y || !ms || n_ms < 1 || patterns < 1 || patterns > 64) return HC_EINVAL;
+    if (n < 1 || n > int64_t(0xFFFFFFFFll)) return HC_EINVAL;
+    for (int32_t i = 0; i < n_ms; ++i)
+        if (ms[i] < 1 || ms[i] > kMaxM || ms[i] > n) return HC_EINVAL;
+    if (!device_info().ok) return HC_EHIP;
+    hipStream_t s = hipStream_t(stream);
+    const int64_t cap = std::min<int64_t>(n, int64_t(1) << 25);
+    int64_t *d_out = nullptr, *d_count = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d_out), size_t(cap) * 8) != hipSuccess) return HC_ENOMEM;
+    if (hipMalloc(reinterpret_cast<void **>(&d_count), 8) != hipSuccess) {
+        (void)hipFree(d_out);
+        return HC_ENOMEM;
+    }
+    hc_status st = HC_OK;
+    uint64_t seed = 0x2310157110ull;
+    const size_t np = size_t(std::max(patterns, 2));
+    for (int32_t i = 0; i < n_ms && st == HC_OK; ++i) {
+        const int64_t m = ms[i];
+        std::vector<std::vector<uint8_t>> pats(np, std::vector<uint8_t>(size_t(m)));
+        for (auto &x : pats) {
+            const int64_t off = int64_t(splitmix(seed) % uint64_t(n - m + 1));
+            if (hipMemcpy(x.data(), d_y + off, size_t(m), hipMemcpyDeviceToHost) != hipSuccess) st = HC_EHIP;
+        }
+        if (st != HC_OK) break;
+        // phase 1: every (q, alpha, w, schedule), two patterns
+        std::vector<Cand> cs = candidates(m);
+        for (Cand &c : cs) {
+            st = time_candidate(c, pats, 2, d_y, n, d_out, cap, d_count, s, &c.ms);
+            if (st != HC_OK) break;
+        }
+        if (st != HC_OK) break;
+        std::sort(cs.begin(), cs.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+        // phase 2: the best four with several segments, all sample patterns
+        Cand best{0, 0, 0, 0, 0};
+        best.ms = 1e30;
+        for (size_t k = 0; k < std::min<size_t>(4, cs.size()) && st == HC_OK; ++k)
+            for (int seg : {64, 100, 132, 200}) {
+                Cand c = cs[k];
+                c.segment = seg;
+                st = time_candidate(c, pats, np, d_y, n, d_out, cap, d_count, s, &c.ms);
+                if (st != HC_OK) break;
+                if (c.ms < best.ms) best = c;
+            }
+        if (st != HC_OK) break;
+        Tuned t;
+        t.set = true;
+        t.q = best.q;
+        t.alpha = best.alpha;
+        t.w = best.w;
+        t.schedule = best.schedule;
+        t.segment = best.segment;
+        set_tuned(m, t);
+        if (out) {
+            out[i].m = m;
+            out[i].params = hc_params{best.q, best.alpha, best.w};
+            out[i].launch = hc_launch{best.segment, best.schedule, HC_VARIANT_HC, 0};
+            out[i].gbps = double(n) / (best.ms * 1e-3) / 1e9;
+        }
+    }
+    (void)hipFree(d_out);
+    (void)hipFree(d_count);
+    return st;
+}
+
+extern "C" void hc_autotune_reset(void) {
+    for (int b = 0; b < kBuckets; ++b) set_tuned(int64_t(1) << b, Tuned{});
+}

@@ -459,6 +459,40 @@ struct TileResult {
     uint32_t total, mine, w0, w1;
 };
 
+// After the marking phase and a barrier: compares the tile's marked windows
+// with x, keeps the occurrences in the bitmap and counts them (this thread's
+// words [w0, w1), its exclusive offset and the tile total). Reads and resets
+// the candidate flags, which alternate between two LDS words per call.
+__device__ __forceinline__ TileResult verify_tile(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                  const uint32_t *__restrict__ x32, const PatternView &P,
+                                                  uint32_t S, uint32_t *bm, uint32_t *misc, uint32_t &it,
+                                                  bool exact = false) {
+    const uint32_t tid = threadIdx.x;
+    const bool has = misc[8 + (it & 1u)] != 0u;
+    if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;   // flag of the next call
+    ++it;
+    TileResult R{0u, 0u, 0u, 0u};
+    if (!has) return R;                           // most tiles: no candidate at all
+    // compare candidates with x; count this thread's share of the tile
+    const uint32_t words = (S + 31u) / 32u;
+    const uint32_t wpt = (words + kThreads - 1u) / kThreads;
+    R.w0 = min(words, tid * wpt);
+    R.w1 = min(words, R.w0 + wpt);
+    uint32_t c = 0;
+    for (uint32_t i = R.w0; i < R.w1; ++i) {
+        uint32_t b = bm[i], keep = b;
+        while (b && !exact) {   // exact: the marks were compared with x already
+            const uint32_t bit = __builtin_ctz(b);
+            b &= b - 1u;
+            if (!window_equals(t32, tb + i * 32u + bit, x32, P.m)) keep &= ~(1u << bit);
+        }
+        bm[i] = keep;
+        c += __popc(keep);
+    }
+    R.mine = block_exclusive_scan(c, misc, &R.total);
+    return R;
+}
+
 template <int Q, typename WT, int K>
 __device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t32, uint32_t tb,
                                                   const WT *__restrict__ F,
@@ -501,29 +535,95 @@ __device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t
             lds_barrier();
         }
     }
-    const bool has = *any != 0u;
-    if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;   // flag of the next call
-    ++it;
-    TileResult R{0u, 0u, 0u, 0u};
-    if (!has) return R;                           // most tiles: no candidate at all
-    // compare candidates with x; count this thread's share of the tile
-    const uint32_t words = (S + 31u) / 32u;
-    const uint32_t wpt = (words + kThreads - 1u) / kThreads;
-    R.w0 = min(words, tid * wpt);
-    R.w1 = min(words, R.w0 + wpt);
-    uint32_t c = 0;
-    for (uint32_t i = R.w0; i < R.w1; ++i) {
-        uint32_t b = bm[i], keep = b;
-        while (b) {
-            const uint32_t bit = __builtin_ctz(b);
-            b &= b - 1u;
-            if (!window_equals(t32, tb + i * 32u + bit, x32, P.m)) keep &= ~(1u << bit);
+    return verify_tile(t32, tb, x32, P, S, bm, misc, it);
+}
+
+// Dense schedule: the test of the searching loop (first word nonzero, each
+// q-gram of the chain linked to the next, last hash equal to H_v), applied to
+// every window of the tile rather than only to the windows the shifts land
+// on. A shift only skips windows that fail this test, and verification
+// removes every non-occurrence, so the result is the same. Each lane takes 8
+// consecutive window starts at a time: it loads the text around them once,
+// hashes the 8 window-end q-grams and the C * q q-gram ends behind them
+// (C = m / q - 1 links per window), looks up their words, and writes the 8
+// outcomes as one bitmap byte. Everything is branch-free, so no lane waits
+// for another's shift: this pays when shifts (m - q + 1) are short.
+// With no links (m < 2q) the test is H(window-end q-gram) = H_v alone: the
+// word F[H_v] is never empty (H_v hashes one of the first q q-grams of x,
+// which is linked or marked). With m <= 4 the whole window is in the word
+// already loaded, so it is compared with x right there and the verification
+// pass only counts.
+template <int Q, typename WT, int C>
+__device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                 const WT *__restrict__ F, const uint32_t *__restrict__ x32,
+                                                 const PatternView &P, uint32_t S, uint32_t *bm, uint32_t *misc,
+                                                 uint32_t &it) {
+    static_assert(Q >= 1 && Q <= 4, "dense schedule hashes 4-byte words");
+    constexpr int E = 8 + C * Q;                  // q-gram ends per group of 8 windows
+    constexpr int NW = ((E - 1) >> 2) + 2;        // aligned words covering them
+    constexpr int Z0 = C > 0 ? Q : 0;             // first q-gram end whose word is needed
+    uint8_t *bm8 = reinterpret_cast<uint8_t *>(bm);
+    const uint32_t groups = (S + 7u) / 8u;
+    const bool inline_check = P.m <= 4u;
+    // x's m bytes as the top m bytes of a word ending at the window end
+    const uint32_t xw = inline_check ? (x32[0] << (8u * (4u - P.m))) : 0u;
+    const uint32_t xmask = inline_check ? (0xFFFFFFFFu << (8u * (4u - P.m))) : 0u;
+    bool found = false;
+    for (uint32_t g = threadIdx.x; g < groups; g += kThreads) {
+        const uint32_t st0 = 8u * g;
+        // LDS position of the earliest q-gram end needed, and the first byte
+        // of the 4-byte word that ends there
+        const uint32_t a0 = tb + st0 + P.m - 1u - uint32_t(C * Q);
+        const uint32_t p0 = a0 - 3u, base = p0 >> 2, sh = p0 & 3u;
+        uint32_t d[NW + 1];
+#pragma unroll
+        for (int i = 0; i <= NW; ++i) d[i] = t32[base + i];
+        uint32_t w[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+        uint32_t h[E], wend[8];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            // bytes a0 + j - 3 .. a0 + j
+            const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
+                                          : w[j >> 2];
+            if (j >= C * Q) wend[j - C * Q] = word;
+            uint32_t v = 0;
+#pragma unroll
+            for (int k = Q - 1; k >= 0; --k) v = (v << P.s) + __builtin_amdgcn_ubfe(word, 8 * (4 - Q + k), 8);
+            h[j] = v & P.mask;
         }
-        bm[i] = keep;
-        c += __popc(keep);
+        uint32_t bits = 0;
+        if constexpr (C == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bits |= uint32_t(h[j] == P.hv) << j;
+        } else {
+            WT z[E - Z0];
+#pragma unroll
+            for (int j = Z0; j < E; ++j) z[j - Z0] = F[h[j]];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = j + C * Q;          // index of the window-end q-gram
+                bool alive = z[e - Z0] != 0;
+#pragma unroll
+                for (int k = 1; k <= C; ++k) alive = alive && linked(z[e - (k - 1) * Q - Z0], h[e - k * Q]);
+                alive = alive && h[e - C * Q] == P.hv;
+                bits |= uint32_t(alive) << j;
+            }
+        }
+        if (inline_check) {
+            uint32_t eq = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) eq |= uint32_t((wend[j] & xmask) == xw) << j;
+            bits &= eq;
+        }
+        if (st0 + 8u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
+        bm8[g] = uint8_t(bits);
+        found |= bits != 0u;
     }
-    R.mine = block_exclusive_scan(c, misc, &R.total);
-    return R;
+    if (found) misc[8 + (it & 1u)] = 1u;
+    lds_barrier();
+    return verify_tile(t32, tb, x32, P, S, bm, misc, it, inline_check);
 }
 
 }  // namespace hc

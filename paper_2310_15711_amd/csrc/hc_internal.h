@@ -32,6 +32,17 @@ struct PatternData {
     std::vector<uint64_t> F;  // 2^alpha words, low w bits used
 };
 
+// Parameters and launch shape chosen by hc_autotune for one pattern-length
+// bucket (lengths in (2^(b-1), 2^b]); process-wide, last tuning wins.
+struct Tuned {
+    bool set = false;
+    int q = 0, alpha = 0, w = 0, schedule = 0, segment = 0;
+};
+constexpr int kBuckets = 13;   // m up to 4096
+int m_bucket(int64_t m);
+void set_tuned(int64_t m, const Tuned &t);
+Tuned get_tuned(int64_t m);
+
 int alpha_max(int w);
 hc_status validate_params(int64_t m, int q, int alpha, int w);
 void default_params(int64_t m, int distinct, int &q, int &alpha, int &w);

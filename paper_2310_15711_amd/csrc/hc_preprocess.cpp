@@ -14,6 +14,7 @@
 // and the links are read from it; OR is order-independent, so F is the same.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "hc_internal.h"
 
@@ -34,13 +35,35 @@ hc_status validate_params(int64_t m, int q, int alpha, int w) {
     return HC_OK;
 }
 
+namespace {
+std::mutex g_tuned_mu;
+Tuned g_tuned[kBuckets];
+}  // namespace
+
+int m_bucket(int64_t m) {
+    int b = 0;
+    while ((int64_t(1) << b) < m && b < kBuckets - 1) ++b;
+    return b;
+}
+
+void set_tuned(int64_t m, const Tuned &t) {
+    std::lock_guard<std::mutex> g(g_tuned_mu);
+    g_tuned[m_bucket(m)] = t;
+}
+
+Tuned get_tuned(int64_t m) {
+    std::lock_guard<std::mutex> g(g_tuned_mu);
+    return g_tuned[m_bucket(m)];
+}
+
 // Built-in priors when the caller leaves a parameter at 0, keyed by the
 // pattern length and the number of distinct bytes of x (a stand-in for the
 // alphabet of the text). Section 4 reports best variants with q between 3 and
 // 8 and alpha 11-12; on gfx950 the fastest choices measured on iid texts over
 // 4 and 64 symbols were: longer q-grams for small alphabets, smaller tables
-// (alpha 11, 16-bit words: more workgroups fit in LDS) for m up to 128. A
-// tuned entry (hc_autotune) takes precedence.
+// (alpha 11, 16-bit words: more workgroups fit in LDS) for m up to 128. An
+// entry measured by hc_autotune for the pattern's length bucket takes
+// precedence.
 void default_params(int64_t m, int distinct, int &q, int &alpha, int &w) {
     const bool small_sigma = distinct <= 4;
     int pq, pa, pw;
@@ -51,6 +74,12 @@ void default_params(int64_t m, int distinct, int &q, int &alpha, int &w) {
     else if (m <= 128) { pq = 5; pa = 11; pw = 16; }
     else if (m <= 256) { pq = 5; pa = 12; pw = 32; }
     else { pq = 6; pa = 12; pw = 32; }
+    const Tuned t = get_tuned(m);
+    if (t.set) {   // a tuned entry for this length bucket takes precedence
+        pq = t.q;
+        pa = t.alpha;
+        pw = t.w;
+    }
     if (q == 0) q = int(std::min<int64_t>(pq, m));
     if (w == 0) w = pw;
     if (alpha == 0) alpha = std::min(pa, alpha_max(w));

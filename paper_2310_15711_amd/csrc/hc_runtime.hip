@@ -113,10 +113,10 @@ hc_status pattern_on_device(hc_pattern *p, const DeviceCopy **out) {
 hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req) {
     hc_launch lc{0, 0, 0, 0};
     if (req) lc = *req;
-    if (lc.segment <= 0) lc.segment = 100;   // tile of 25600 starts; 100/4 is odd
-    if (lc.schedule == HC_SCHED_AUTO) lc.schedule = HC_SCHED_SEGMENT;
+    const Tuned t = get_tuned(p.m);
+    if (lc.segment <= 0) lc.segment = t.set ? t.segment : 100;   // tile of 25600 starts
+    if (lc.schedule == HC_SCHED_AUTO) lc.schedule = t.set ? t.schedule : HC_SCHED_SEGMENT;
     if (lc.variant == HC_VARIANT_AUTO) lc.variant = HC_VARIANT_HC;
-    (void)p;
     (void)n;
     return lc;
 }
@@ -194,7 +194,7 @@ hc_status hc_search_async(const hc_pattern *pc, const uint8_t *d_y, int64_t n, i
     if (n > 0 && !d_y) return HC_EINVAL;
     if (n > int64_t(0xFFFFFFFFll)) return HC_EINVAL;
     if (launch && (launch->segment < 0 || launch->segment > 4096 || launch->schedule < 0 ||
-                   launch->schedule > HC_SCHED_WAVE || launch->variant < 0 ||
+                   launch->schedule > HC_SCHED_DENSE || launch->variant < 0 ||
                    launch->variant > HC_VARIANT_SPARSE || launch->wg_per_cu < 0 ||
                    launch->wg_per_cu > 8))
         return HC_EINVAL;

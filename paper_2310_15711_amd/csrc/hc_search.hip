@@ -133,6 +133,13 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
                 }
                 mine = block_exclusive_scan(c, misc, &total);
             }
+        } else if constexpr (SCHED >= HC_SCHED_DENSE) {   // dense, C = SCHED - HC_SCHED_DENSE
+            const TileResult R = dense_tile<(Q <= 4 ? Q : 4), WT, (SCHED - HC_SCHED_DENSE)>(
+                t32, tb_cur, F, x32, P, S, bm, misc, it);
+            total = R.total;
+            mine = R.mine;
+            w0 = R.w0;
+            w1 = R.w1;
         } else {
             const TileResult R = search_tile<Q, WT, K>(t32, tb_cur, F, x32, P, S, A.seg, bm, park,
                                                        misc, it, round);
@@ -269,6 +276,13 @@ static int lookahead_for(uint32_t shift) { return shift <= 12 ? 4 : 1; }
 template <int Q, typename WT>
 static KernelFn pick_sched(int sched, int K) {
     if (sched == HC_SCHED_WAVE) return hc_search_kernel<Q, WT, HC_SCHED_WAVE, 1>;
+    if constexpr (Q <= 4) {
+        // dense: one instance per number of links per window (0..3)
+        if (sched == HC_SCHED_DENSE + 0) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 0, 1>;
+        if (sched == HC_SCHED_DENSE + 1) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 1, 1>;
+        if (sched == HC_SCHED_DENSE + 2) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 2, 1>;
+        if (sched == HC_SCHED_DENSE + 3) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 3, 1>;
+    }
     return K == 4 ? hc_search_kernel<Q, WT, HC_SCHED_SEGMENT, 4>
                   : hc_search_kernel<Q, WT, HC_SCHED_SEGMENT, 1>;
 }
@@ -339,7 +353,14 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
     if (st != HC_OK) return st;
 
-    KernelFn fn = pick_kernel(pd.q, pd.w, lc.schedule, lookahead_for(m - uint32_t(pd.q) + 1u));
+    // the dense schedule is instantiated for q <= 4 and up to 3 links per
+    // window; other patterns run the searching loop
+    int sched = lc.schedule;
+    if (sched == HC_SCHED_DENSE) {
+        const int links = int(m) / pd.q - 1;
+        sched = (pd.q <= 4 && links <= 3) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;
+    }
+    KernelFn fn = pick_kernel(pd.q, pd.w, sched, lookahead_for(m - uint32_t(pd.q) + 1u));
     int per_cu = occupancy(fn, L.total);
     if (lc.wg_per_cu > 0) per_cu = std::min(per_cu, int(lc.wg_per_cu));
     uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, int64_t(di.cus) * per_cu)));

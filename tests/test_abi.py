@@ -112,3 +112,21 @@ def test_null_arguments_are_rejected():
     cnt = ctypes.c_int64()
     assert L.hc_search(None, None, 0, None, 0, ctypes.byref(cnt), None) == B.HC_EINVAL
     L.hc_pattern_free(None)
+    # argument checks that come before any device call
+    ms = (ctypes.c_int64 * 1)(8)
+    assert L.hc_autotune(None, 1 << 20, ms, 1, 3, None, None) == B.HC_EINVAL
+    assert L.hc_autotune(ctypes.c_void_p(16), 1 << 20, ms, 0, 3, None, None) == B.HC_EINVAL
+    assert L.hc_autotune(ctypes.c_void_p(16), 1 << 20, ms, 1, 0, None, None) == B.HC_EINVAL
+    big = (ctypes.c_int64 * 1)(4097)
+    assert L.hc_autotune(ctypes.c_void_p(16), 1 << 20, big, 1, 3, None, None) == B.HC_EINVAL
+    assert L.hc_serve_next_done(None, None, 0) == B.HC_EINVAL
+    L.hc_autotune_reset()
+
+
+def test_bucket_defaults_after_reset():
+    """With no tuned entries the priors apply; q never exceeds m."""
+    B.hc_autotune_reset()
+    for m in (1, 2, 3, 5, 17, 100, 1000, 4096):
+        p = B.hc_preprocess(bytes((7 * i) % 256 for i in range(m)))
+        info = B.hc_pattern_info(p)
+        assert 1 <= info["q"] <= min(m, 8)

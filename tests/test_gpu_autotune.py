@@ -1,0 +1,76 @@
+"""The autotuner (hc_autotune through the C ABI): its choices are valid, they
+become the defaults of the tuned length buckets, and searches and batches run
+with them stay identical to the oracle's brute force."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hc_oracle as O
+from paper_2310_15711_amd import binding as B
+from paper_2310_15711_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def text():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    y = W.iid_text(24 << 20, W.ALPHABETS[4], W.rng(W.TEST_CFG, 0, 41))
+    return y, torch.from_numpy(y).to("cuda:0")
+
+
+def test_autotune_choices_are_used_and_exact(text):
+    y, yd = text
+    lengths = [2, 4, 8, 32, 300]
+    announce("autotune", lengths)
+    try:
+        tuned = B.hc_autotune(yd, lengths, patterns=3)
+        assert [t["m"] for t in tuned] == lengths
+        for t in tuned:
+            q, alpha, w = t["params"]
+            seg, sched, variant, wg = t["launch"]
+            assert 1 <= q <= min(t["m"], 8)
+            assert (alpha, w) in {(8, 8), (10, 16), (11, 16), (12, 16), (12, 32)}
+            assert sched in (B.HC_SCHED_SEGMENT, B.HC_SCHED_DENSE) and seg in (64, 100, 132, 200)
+            assert t["gbps"] > 0
+        rs = np.random.default_rng(3)
+        for t in tuned:
+            m = t["m"]
+            for _ in range(3):
+                off = int(rs.integers(0, y.size - m))
+                x = y[off:off + m].tobytes()
+                p = B.hc_preprocess(x)   # defaults: the tuned entry of m's bucket
+                info = B.hc_pattern_info(p)
+                assert (info["q"], info["alpha"], info["w"]) == t["params"]
+                announce("tuned search", m, off)
+                got = B.find_all(p, yd).cpu().numpy()
+                assert np.array_equal(got, O.occurrences(x, y))
+        # a batch after tuning: q per pattern from the tuned buckets
+        import torch
+
+        texts = [y[: 3 << 20], y[5 << 20: 6 << 20]]
+        off = np.array([0, texts[0].size, texts[0].size + texts[1].size], dtype=np.int64)
+        d_text = torch.from_numpy(np.concatenate(texts)).to("cuda:0")
+        pats = [y[o:o + m].tobytes() for o, m in ((100, 4), (7000, 32), (99999, 300), (12, 2))]
+        pairs = [(p, t) for p in range(len(pats)) for t in range(len(texts))]
+        want = [O.occurrences(pats[p], texts[t]) for p, t in pairs]
+        total_want = sum(w.size for w in want)
+        d_pos = torch.empty(total_want + 1, dtype=torch.int64, device="cuda:0")
+        d_off = torch.empty(len(pairs) + 1, dtype=torch.int64, device="cuda:0")
+        announce("tuned batch")
+        st, total = B.hc_search_batched(d_text, off, pats, [p for p, _ in pairs], [t for _, t in pairs],
+                                        d_pos, d_off)
+        assert st == B.HC_OK and total == total_want
+        po = d_off.cpu().numpy()
+        pos = d_pos.cpu().numpy()
+        for k, w in enumerate(want):
+            assert np.array_equal(pos[po[k]:po[k + 1]], w), pairs[k]
+    finally:
+        B.hc_autotune_reset()

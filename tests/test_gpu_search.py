@@ -63,7 +63,7 @@ def test_hand_cases(torch_dev):
         assert got == want, (xh, yh)
 
 
-SCHEDS = [B.HC_SCHED_SEGMENT, B.HC_SCHED_WAVE]
+SCHEDS = [B.HC_SCHED_SEGMENT, B.HC_SCHED_WAVE, B.HC_SCHED_DENSE]
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
@@ -187,7 +187,7 @@ def test_parameter_invariance(torch_dev):
         yd = to_dev(y, torch_dev)
         for q in sorted({1, 2, min(m, 4), min(m, 8)}):
             for alpha, w in ((4, 8), (11, 16), (12, 32), (13, 64)):
-                for seg, sched in ((16, 1), (132, 1), (64, 2)):
+                for seg, sched in ((16, 1), (132, 1), (64, 2), (100, 3)):
                     announce("invariance", m, q, alpha, w, seg, sched)
                     got, c = gpu_occ(x, yd, (q, alpha, w), (seg, sched, 0, 0))
                     assert np.array_equal(got, want), (m, q, alpha, w, seg, sched)
