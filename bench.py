@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--params", default=None, help="q,alpha,w for every pattern")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip hc_autotune (built-in priors choose q, alpha, w and the launch shape)")
+    ap.add_argument("--tune-patterns", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patterns", type=int, default=12,
                     help="oracle sample: patterns per (sigma, m)")
@@ -441,8 +444,21 @@ def main():
 
     dtexts = {s: torch.from_numpy(y).to(dev) for s, y in texts.items()}
     params = tuple(int(v) for v in args.params.split(",")) if args.params else None
-    handles = [B.hc_preprocess(x, params) for (_, _, _, x) in pats]
     launch = (args.segment, args.schedule, args.variant, args.wg_per_cu)
+    # autotuning (outside the timed region): per text, the fastest q, alpha,
+    # w, schedule and segment for each pattern length, measured by the
+    # library on patterns of its own choosing from that text
+    tuned, tune_s = {}, 0.0
+    if not args.no_tune and params is None and launch == (0, 0, 0, 0):
+        t0 = time.time()
+        for s_, yd in dtexts.items():
+            ms = sorted({m for (s2, m, _, _) in pats if s2 == s_})
+            tuned[s_] = {r["m"]: r for r in B.hc_autotune(yd, ms, patterns=args.tune_patterns)}
+        tune_s = time.time() - t0
+        B.hc_autotune_reset()
+        log(f"autotuned in {tune_s:.1f}s")
+    handles = [B.hc_preprocess(x, tuned[s][m]["params"] if tuned else params) for (s, m, _, x) in pats]
+    launches = [tuned[s][m]["launch"] if tuned else launch for (s, m, _, _) in pats]
     cap = 1 << 25
     out = torch.empty(cap, dtype=torch.int64, device=dev)
     counts = torch.zeros(len(pats), dtype=torch.int64, device=dev)
@@ -454,7 +470,7 @@ def main():
         for i, (s, m, off, x) in enumerate(pats):
             if k is not None:
                 ev0[k][i].record(stream)
-            B.hc_search_async(handles[i], dtexts[s], out, counts[i:i + 1], launch=launch,
+            B.hc_search_async(handles[i], dtexts[s], out, counts[i:i + 1], launch=launches[i],
                               stream=stream)
             if k is not None:
                 ev1[k][i].record(stream)
@@ -549,7 +565,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "launches_per_step": len(pats),
                    "text_bytes_per_step": text_bytes, "occurrences_per_step": int(cnt.sum()),
-                   "wall_s": round(wall, 3)},
+                   "wall_s": round(wall, 3),
+                   "autotune": ({"seconds": round(tune_s, 1),
+                                 "choice": {f"{s_}/{m}": {"q_alpha_w": list(r["params"]),
+                                                          "segment": r["launch"][0],
+                                                          "schedule": r["launch"][1]}
+                                            for s_, d in tuned.items() for m, r in d.items()}}
+                                if tuned else None)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail_median_text_gbps": detail,
