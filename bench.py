@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip hc_autotune (built-in priors choose q, alpha, w and the launch shape)")
     ap.add_argument("--tune-patterns", type=int, default=5)
+    ap.add_argument("--save-tuned", default=None, help="write the autotuned choices to this JSON file")
+    ap.add_argument("--load-tuned", default=None,
+                    help="use the choices in this JSON file instead of tuning (profiling runs)")
+    ap.add_argument("--lds-dir", default=None, help="with --summarize: rocprofv3 LDS counter pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patterns", type=int, default=12,
                     help="oracle sample: patterns per (sigma, m)")
@@ -132,6 +136,29 @@ def _counter_per_dispatch(d, counter, name_part):
     return (sum(per.values()) / len(per)) if per else None, len(per)
 
 
+def summarize_lds(lds_dir, cmd):
+    """LDS bank conflicts of the search kernels from a rocprofv3 --pmc pass."""
+    rows = _read_csv(_find(lds_dir, "counter_collection.csv"))
+    tot = {}
+    for r in rows:
+        if "hc_search_kernel" in r["Kernel_Name"]:
+            tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    conf, active = tot.get("SQ_LDS_BANK_CONFLICT", 0.0), tot.get("SQ_ACTIVE_INST_LDS", 0.0)
+    insts = tot.get("SQ_INSTS_LDS", 0.0)
+    lines = ["# LDS bank conflicts of the single-pattern search kernels (rocprofv3 --pmc)", "",
+             "Command(s):", "", "```", cmd.strip(), "```", "",
+             "| counter (summed over hc_search_kernel dispatches) | value |", "|---|---|"]
+    lines += [f"| {k} | {v:.0f} |" for k, v in sorted(tot.items())]
+    lines += ["", f"- Bank-conflict cycles per cycle of LDS instruction activity "
+                  f"(SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS): {conf / active:.3f}" if active else "",
+              f"- Bank-conflict cycles per LDS instruction (SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS): "
+              f"{conf / insts:.3f}" if insts else "", ""]
+    with open(os.path.join(ROOT, "profiles", "hc_search_single_pattern_lds.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return {"lds_conflict_per_active_cycle": conf / active if active else None,
+            "lds_conflict_cycles_per_inst": conf / insts if insts else None}
+
+
 def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
     stats = _read_csv(_find(stats_dir, "kernel_stats.csv"))
     lines = ["# rocprofv3 kernel statistics: single-pattern HC search, sigma in {4,20,64}, "
@@ -163,8 +190,9 @@ def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
     fetch_e, _ = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "hc_emit_kernel")
     write_s, nw = _counter_per_dispatch(write_dir, "WRITE_SIZE", "hc_search_kernel")
     write_e, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", "hc_emit_kernel")
-    cf, _ = _counter_per_dispatch(calib_prefix + "_fetch", "FETCH_SIZE", "")
-    cw, _ = _counter_per_dispatch(calib_prefix + "_write", "WRITE_SIZE", "")
+    # the copy kernel only (the fills that create the sources read nothing)
+    cf, _ = _counter_per_dispatch(calib_prefix + "_fetch", "FETCH_SIZE", "copyBuffer")
+    cw, _ = _counter_per_dispatch(calib_prefix + "_write", "WRITE_SIZE", "copyBuffer")
     copy_bytes = 256 << 20
     kf = copy_bytes / (cf * 1024.0)    # bytes per counted KiB
     kw = copy_bytes / (cw * 1024.0)
@@ -181,10 +209,13 @@ def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
              "Command(s):", "", "```", cmd.strip(), "```", "",
              f"- FETCH_SIZE per call (search + emit kernels): {(fetch_s or 0) + (fetch_e or 0):.0f} KiB "
              f"over {nf} calls; WRITE_SIZE per call: {(write_s or 0) + (write_e or 0):.0f} KiB.",
-             f"- Calibration: a plain 256 MiB device copy reads FETCH_SIZE = {cf:.0f} KiB and "
-             f"WRITE_SIZE = {cw:.0f} KiB (ideal 262144 KiB each); scale factors {kf:.4f} and {kw:.4f}.",
+             f"- Calibration: a plain 256 MiB device copy (`__amd_rocclr_copyBuffer`, sources "
+             f"rotated over 1 GiB) reads FETCH_SIZE = {cf:.0f} KiB and WRITE_SIZE = {cw:.0f} KiB "
+             f"per dispatch (it moves 262144 KiB each way); scale factors {kf:.4f} and {kw:.4f}.",
              f"- Scaled HBM bytes per call: fetch {fetch/1e6:.1f} MB + write {write/1e6:.1f} MB = "
-             f"{(fetch + write)/1e6:.1f} MB.", ""]
+             f"{(fetch + write)/1e6:.1f} MB.",
+             "- Workload: the bench's single-pattern mix (sigma 4/20/64, m 2..1024), 10 patterns "
+             "per (sigma, m), with the tuned choices in `hc_search_single_pattern_tuned.json`.", ""]
     with open(os.path.join(ROOT, "profiles", "hc_search_single_pattern_traffic.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print(json.dumps(tj))
@@ -382,6 +413,8 @@ def main():
     args = parse()
     if args.summarize:
         summarize(*args.summarize, args.summary_cmd)
+        if args.lds_dir:
+            print(json.dumps(summarize_lds(args.lds_dir, args.summary_cmd)))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -449,7 +482,12 @@ def main():
     # w, schedule and segment for each pattern length, measured by the
     # library on patterns of its own choosing from that text
     tuned, tune_s = {}, 0.0
-    if not args.no_tune and params is None and launch == (0, 0, 0, 0):
+    if args.load_tuned:
+        with open(args.load_tuned) as f:
+            raw = json.load(f)
+        tuned = {int(s_): {int(m): {"params": tuple(r["params"]), "launch": tuple(r["launch"])}
+                           for m, r in d.items()} for s_, d in raw.items()}
+    elif not args.no_tune and params is None and launch == (0, 0, 0, 0):
         t0 = time.time()
         for s_, yd in dtexts.items():
             ms = sorted({m for (s2, m, _, _) in pats if s2 == s_})
@@ -457,6 +495,10 @@ def main():
         tune_s = time.time() - t0
         B.hc_autotune_reset()
         log(f"autotuned in {tune_s:.1f}s")
+        if args.save_tuned:
+            with open(args.save_tuned, "w") as f:
+                json.dump({str(s_): {str(m): {"params": list(r["params"]), "launch": list(r["launch"])}
+                                     for m, r in d.items()} for s_, d in tuned.items()}, f, indent=1)
     handles = [B.hc_preprocess(x, tuned[s][m]["params"] if tuned else params) for (s, m, _, x) in pats]
     launches = [tuned[s][m]["launch"] if tuned else launch for (s, m, _, _) in pats]
     cap = 1 << 25
@@ -525,7 +567,8 @@ def main():
 
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "hc_search_kernel", "avg_launch_us": round(avg_launch_ms * 1e3, 2),
+                "kernel": "hc_search_kernel + hc_emit_kernel (one search call)",
+                "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                 "alg_bytes_per_launch": round(float(alg_bytes.mean()))}
 
     cpu = None
