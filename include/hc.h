@@ -147,6 +147,27 @@ hc_status hc_pattern_info(const hc_pattern *p, hc_params *used, int32_t *s,
 void hc_pattern_free(hc_pattern *p);
 
 /*
+ * hc_preprocess_many -- the preprocessing phase (as hc_preprocess) for n
+ * patterns at once, computed on the device: one workgroup per pattern sets
+ * the links of eq. (1) with atomic ORs in on-chip memory, then, after a
+ * barrier, the first-q marks of eq. (2) into words still empty (Section 3.4),
+ * and writes F as 2^alpha packed w-bit words (little-endian, the layout of
+ * hc_pattern_info's words truncated to w bits) at d_F + i * table_stride.
+ *   pat/pat_off  (host) pattern bytes and n + 1 offsets; 1 <= m <= 4096;
+ *   params       alpha and w shared by all patterns (0 = 12 and 32); q per
+ *                pattern (0 = library choice, capped at m);
+ *   d_F          device memory of n * table_stride bytes (caller-owned);
+ *   table_stride a multiple of 16, >= max(16, 2^alpha * w / 8), at most the
+ *                on-chip memory of one workgroup (160 KiB);
+ *   used, info   (host, may be NULL) per pattern: the parameters used, and
+ *                s, mask, H_v (three uint32 each).
+ * Synchronises `stream`. The tables equal hc_preprocess's bit for bit.
+ */
+hc_status hc_preprocess_many(const uint8_t *pat, const int64_t *pat_off, int32_t n,
+                             const hc_params *params, void *d_F, int64_t table_stride,
+                             hc_params *used, uint32_t *info, void *stream);
+
+/*
  * hc_search -- the searching phase (Section 3.3): all occurrences of the
  * pattern in d_y[0..n-1] (device bytes).
  *   d_out   device int64 array of `cap` entries; receives the first

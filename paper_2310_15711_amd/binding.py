@@ -27,6 +27,7 @@ EXPORTED = (
     "hc_search_batched", "hc_batch_plan_create", "hc_batch_plan_run", "hc_batch_plan_free",
     "hc_serve_create", "hc_serve_submit", "hc_serve_poll", "hc_serve_next_done",
     "hc_serve_stats", "hc_serve_destroy", "hc_strerror", "hc_autotune", "hc_autotune_reset",
+    "hc_preprocess_many",
 )
 
 
@@ -90,6 +91,7 @@ def lib():
         "hc_strerror": (ctypes.c_char_p, [i32]),
         "hc_autotune": (i32, [p, i64, P(i64), i32, i32, p, p]),
         "hc_autotune_reset": (None, []),
+        "hc_preprocess_many": (i32, [p, p, i32, p, p, i64, p, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -379,3 +381,22 @@ def hc_autotune(y_dev, lengths, patterns: int = 5, stream=None) -> list:
 
 def hc_autotune_reset() -> None:
     lib().hc_autotune_reset()
+
+
+def hc_preprocess_many(patterns: Sequence[bytes], d_F, table_stride: int, params=None, stream=None):
+    """Device preprocessing of many patterns into d_F (torch uint8, n * stride
+    bytes). Returns (used params per pattern, (s, mask, hv) per pattern)."""
+    n = len(patterns)
+    if int(d_F.numel()) < n * int(table_stride):
+        raise ValueError("d_F holds fewer than n * table_stride bytes")
+    po = np.zeros(n + 1, dtype=np.int64)
+    po[1:] = np.cumsum([len(x) for x in patterns])
+    pb = np.frombuffer(b"".join(patterns), dtype=np.uint8) if n else np.zeros(1, np.uint8)
+    used = (hc_params * max(n, 1))()
+    info = np.zeros(3 * max(n, 1), dtype=np.uint32)
+    pr = _params(params)
+    _check(lib().hc_preprocess_many(pb.ctypes.data, po.ctypes.data, n, ctypes.byref(pr) if pr is not None else None,
+                                    _dev_ptr(d_F, "torch.uint8"), int(table_stride), used, info.ctypes.data,
+                                    _stream_ptr(stream)), "hc_preprocess_many")
+    return ([(u.q, u.alpha, u.w) for u in used[:n]],
+            [tuple(int(v) for v in info[3 * i:3 * i + 3]) for i in range(n)])

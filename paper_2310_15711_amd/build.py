@@ -31,6 +31,7 @@ SOURCES = [
     "hc_batched.hip",
     "hc_serve.cpp",
     "hc_autotune.cpp",
+    "hc_preprocess_device.hip",
 ]
 
 

@@ -71,7 +71,16 @@ hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint
 // Preprocesses np patterns (CSR pat/pat_off) into packed tables and bytes.
 hc_status pack_patterns(const uint8_t *pat, const int64_t *pat_off, int32_t np, const hc_params *params,
                         int alpha, int w, uint32_t table_bytes, std::vector<BPat> &bp,
-                        std::vector<uint8_t> &Fh, std::vector<uint8_t> &Xh, uint32_t &max_m);
+                        std::vector<uint8_t> &Fh, std::vector<uint8_t> &Xh, uint32_t &max_m, bool host_tables);
+
+// A pattern's descriptor (m, q, s, mask, H_v) without its table.
+hc_status pack_desc(const uint8_t *x, int64_t m, int q_req, int alpha, int w, BPat &bp);
+
+// Builds the word vectors of n patterns on the device (one workgroup each):
+// pattern i's bytes at d_x + desc[3i], length desc[3i+1], q desc[3i+2]; its
+// table at d_F + i * table_bytes; s, mask, H_v into d_info (may be null).
+hc_status device_preprocess(const uint8_t *d_x, const uint32_t *d_desc, uint32_t n, int alpha, int w,
+                            uint32_t table_bytes, uint8_t *d_F, uint32_t *d_info, hipStream_t s);
 
 // One pattern's descriptor, table and bytes (for pools that place x themselves).
 hc_status pack_one(const uint8_t *x, int64_t m, int q_req, int alpha, int w, uint32_t table_bytes,

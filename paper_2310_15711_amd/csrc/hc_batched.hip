@@ -466,11 +466,26 @@ hc_status pack_one(const uint8_t *x, int64_t m, int q_req, int alpha, int w, uin
     return HC_OK;
 }
 
+hc_status pack_desc(const uint8_t *x, int64_t m, int q_req, int alpha, int w, BPat &bp) {
+    if (m < 1 || m > kMaxM) return HC_EINVAL;
+    int q = q_req, a = alpha, ww = w;
+    default_params(m, distinct_bytes(x, m), q, a, ww);
+    q = int(std::min<int64_t>(q, m));
+    if (validate_params(m, q, alpha, w) != HC_OK) return HC_EINVAL;
+    const uint32_t s = uint32_t(alpha / q), mask = uint32_t((uint64_t(1) << alpha) - 1u);
+    // H_v: hash (eq. (3)) of the q-gram at (m - q) mod q
+    const uint8_t *u = x + (m - q) % q;
+    uint32_t v = 0;
+    for (int k = q - 1; k >= 0; --k) v = (v << s) + u[k];
+    bp = BPat{uint32_t(m), uint32_t(q), s, mask, v & mask, 0, 0, 0};
+    return HC_OK;
+}
+
 hc_status pack_patterns(const uint8_t *pat, const int64_t *pat_off, int32_t np, const hc_params *params,
                         int alpha, int w, uint32_t table_bytes, std::vector<BPat> &bp, std::vector<uint8_t> &Fh,
-                        std::vector<uint8_t> &Xh, uint32_t &max_m) {
+                        std::vector<uint8_t> &Xh, uint32_t &max_m, bool host_tables) {
     bp.assign(size_t(std::max(np, 1)), BPat{});
-    Fh.assign(size_t(std::max(np, 1)) * table_bytes, 0);
+    Fh.assign(host_tables ? size_t(std::max(np, 1)) * table_bytes : 0, 0);
     std::vector<uint32_t> xoff(size_t(np) + 1, 0);
     int64_t mmax = 1;
     for (int32_t i = 0; i < np; ++i) {
@@ -485,8 +500,9 @@ hc_status pack_patterns(const uint8_t *pat, const int64_t *pat_off, int32_t np, 
     for (int32_t i = 0; i < np; ++i) {
         const uint8_t *x = pat + pat_off[i];
         const int64_t m = pat_off[i + 1] - pat_off[i];
-        hc_status st = pack_one(x, m, params ? params->q : 0, alpha, w, table_bytes, bp[i],
-                                Fh.data() + size_t(i) * table_bytes);
+        hc_status st = host_tables ? pack_one(x, m, params ? params->q : 0, alpha, w, table_bytes, bp[i],
+                                              Fh.data() + size_t(i) * table_bytes)
+                                   : pack_desc(x, m, params ? params->q : 0, alpha, w, bp[i]);
         if (st != HC_OK) return st;
         bp[i].x_off = xoff[i];
         std::memcpy(Xh.data() + xoff[i], x, size_t(m));
@@ -710,7 +726,7 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
     std::vector<uint8_t> Fh, Xh;
     uint32_t max_m = 1;
     if ((st = pack_patterns(b->pat, b->pat_off, b->n_pats, params, alpha, w, table_bytes, H.pats, Fh, Xh,
-                            max_m)) != HC_OK)
+                            max_m, false)) != HC_OK)
         return st;
     if ((st = batch_geometry(P->D, max_m, table_bytes, uint32_t(w))) != HC_OK) return st;
     H.views.resize(size_t(b->n_texts));
@@ -722,8 +738,20 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
     for (int64_t k = 0; k < b->n_pairs; ++k) pairs[k] = {uint32_t(b->pair_pat[k]), uint32_t(b->pair_text[k])};
     batch_build(H, pairs, P->D.tile, kBatchGroup);
     hipStream_t s = nullptr;
-    if ((st = P->Fpool.upload(Fh.data(), Fh.size(), s)) != HC_OK) return st;
     if ((st = P->xpool.upload(Xh.data(), Xh.size(), s)) != HC_OK) return st;
+    // the word vectors are built on the device from the uploaded pattern bytes
+    if (P->Fpool.ensure(size_t(std::max(b->n_pats, 1)) * table_bytes) != HC_OK) return HC_ENOMEM;
+    std::vector<uint32_t> desc(size_t(b->n_pats) * 3);
+    for (int32_t i = 0; i < b->n_pats; ++i) {
+        desc[3 * i] = H.pats[i].x_off;
+        desc[3 * i + 1] = H.pats[i].m;
+        desc[3 * i + 2] = H.pats[i].q;
+    }
+    DeviceBuf d_desc;
+    if ((st = d_desc.upload(desc.data(), desc.size() * 4, s)) != HC_OK) return st;
+    if ((st = device_preprocess(P->xpool.as<uint8_t>(), d_desc.as<uint32_t>(), uint32_t(b->n_pats), alpha, w,
+                                table_bytes, P->Fpool.as<uint8_t>(), nullptr, s)) != HC_OK)
+        return st;
     P->D.Fs = P->Fpool.as<uint8_t>();
     P->D.xs = P->xpool.as<uint8_t>();
     P->D.Fs_bytes = P->Fpool.bytes;
