@@ -76,9 +76,12 @@ enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENS
  *   sentinel  SHC (Section 3.4, third optimisation): a copy of x is placed
  *             after each text tile in on-chip memory, so the loop over
  *             empty words runs without a position test;
- *   sparse    for long patterns: text is fetched from memory only in the
- *             128-byte lines that hold q-grams the search actually reads,
- *             instead of streaming every tile. */
+ *   sparse    for long patterns: no tile is staged; each lane reads the
+ *             q-grams it hashes (and the windows it verifies) in place, so
+ *             only the cache lines that hold them are fetched; long chain
+ *             walks and verifications are shared by a whole wavefront.
+ *             Tiles hold 256 * segment window starts (segment 0 = 1024, up
+ *             to 4096). The sentinel variant is accepted and runs as hc. */
 enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIANT_SPARSE = 3 };
 
 /* Launch shape of the search kernel. A field set to 0 is chosen by the
@@ -100,11 +103,14 @@ typedef struct hc_pattern hc_pattern;   /* opaque; immutable once built      */
  * every pattern whose length falls in the same bucket (2^(b-1), 2^b]; the
  * last tuning of a bucket wins, process-wide. Candidates: q in [1, min(m,
  * 8)], (alpha, w) in {(8,8), (10,16), (11,16), (12,16), (12,32)}, the segment
- * and dense schedules, segments {64, 100, 132, 200}; timed with `patterns`
+ * and dense schedules, segments {64, 100, 132, 200}, and for m >= 256 the
+ * sparse variant with segments {512, 1024, 2048, 4096}; timed with `patterns`
  * (1..64) patterns copied from the text at fixed pseudo-random offsets.
  * out[i] (may be NULL) receives the choice for ms[i] and its median text
  * GB/s. Runs on `stream` and synchronises it; allocates a scratch output of
- * min(n, 2^25) positions. The choice never changes search results (the
+ * min(n, 2^25) positions and, when it fits, a 512 MiB buffer that is
+ * overwritten before each timed launch (so the text is read from HBM, not
+ * from the last-level cache). The choice never changes search results (the
  * parameters only change speed). Errors: HC_EINVAL on bad arguments.
  * hc_autotune_reset forgets every tuned entry.
  */

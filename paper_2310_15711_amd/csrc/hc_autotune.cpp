@@ -6,9 +6,11 @@
 // For each length m, sample patterns are copied out of the text at fixed
 // pseudo-random offsets (so they occur at least once, like the paper's
 // randomly extracted patterns, Section 4). Phase 1 times every (q, alpha, w,
-// schedule) candidate on two patterns at the default segment; phase 2 times
-// the four best with several segments on all sample patterns. The median
-// time per launch decides. Results never depend on the choice, only speed.
+// schedule, variant) candidate on two patterns at the default segment; phase
+// 2 times the four best with several segments on all sample patterns. A
+// 512 MiB buffer is overwritten before each timed launch so the text comes
+// from HBM. The median time per launch decides. Results never depend on the
+// choice, only speed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +23,7 @@ namespace hc {
 namespace {
 
 struct Cand {
-    int q, alpha, w, schedule, segment;
+    int q, alpha, w, schedule, segment, variant = HC_VARIANT_HC;
     double ms = 0;
 };
 
@@ -40,10 +42,20 @@ struct Timer {
     }
 };
 
+// Buffer overwritten before each timed launch, so that the text is read
+// from HBM as in a run over many texts, not from the 256 MB last-level cache.
+struct Flush {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~Flush() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 // Median milliseconds per launch of one candidate over `pats`.
 hc_status time_candidate(const Cand &c, const std::vector<std::vector<uint8_t>> &pats, size_t np,
                          const uint8_t *d_y, int64_t n, int64_t *d_out, int64_t cap, int64_t *d_count,
-                         hipStream_t s, double *ms) {
+                         const Flush &fl, hipStream_t s, double *ms) {
     std::vector<hc_pattern *> hs;
     hc_status st = HC_OK;
     for (size_t i = 0; i < np && st == HC_OK; ++i) {
@@ -52,11 +64,15 @@ hc_status time_candidate(const Cand &c, const std::vector<std::vector<uint8_t>> 
         st = hc_preprocess(pats[i].data(), int64_t(pats[i].size()), &prm, &p);
         if (st == HC_OK) hs.push_back(p);
     }
-    const hc_launch lc{c.segment, c.schedule, HC_VARIANT_HC, 0};
+    const hc_launch lc{c.segment, c.schedule, c.variant, 0};
     std::vector<Timer> ev(hs.size());
     if (st == HC_OK && !hs.empty())   // warm-up: uploads the table, loads the kernel
         st = hc_search_async(hs[0], d_y, n, d_out, cap, d_count, &lc, s);
     for (size_t i = 0; i < hs.size() && st == HC_OK; ++i) {
+        if (fl.p && hipMemsetAsync(fl.p, int(i & 0xFF), fl.bytes, s) != hipSuccess) {
+            st = HC_EHIP;
+            break;
+        }
         if (hipEventCreate(&ev[i].a) != hipSuccess || hipEventCreate(&ev[i].b) != hipSuccess ||
             hipEventRecord(ev[i].a, s) != hipSuccess) {
             st = HC_EHIP;
@@ -87,6 +103,9 @@ std::vector<Cand> candidates(int64_t m) {
             if (aw[0] > alpha_max(aw[1])) continue;
             out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, 100});
             if (q <= 4 && m / q - 1 <= 3) out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_DENSE, 100});
+            // long patterns: text read in place (most cache lines never fetched)
+            if (m >= 256 && q >= 3)
+                out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, 1024, HC_VARIANT_SPARSE});
         }
     return out;
 }
@@ -111,6 +130,12 @@ extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *m
         (void)hipFree(d_out);
         return HC_ENOMEM;
     }
+    Flush fl;   // best effort: without it the timings are cache-warm
+    fl.bytes = size_t(512) << 20;
+    if (hipMalloc(&fl.p, fl.bytes) != hipSuccess) {
+        fl.p = nullptr;
+        (void)hipGetLastError();
+    }
     hc_status st = HC_OK;
     uint64_t seed = 0x2310157110ull;
     const size_t np = size_t(std::max(patterns, 2));
@@ -125,19 +150,21 @@ extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *m
         // phase 1: every (q, alpha, w, schedule), two patterns
         std::vector<Cand> cs = candidates(m);
         for (Cand &c : cs) {
-            st = time_candidate(c, pats, 2, d_y, n, d_out, cap, d_count, s, &c.ms);
+            st = time_candidate(c, pats, 2, d_y, n, d_out, cap, d_count, fl, s, &c.ms);
             if (st != HC_OK) break;
         }
         if (st != HC_OK) break;
         std::sort(cs.begin(), cs.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
         // phase 2: the best four with several segments, all sample patterns
-        Cand best{0, 0, 0, 0, 0};
+        Cand best{0, 0, 0, 0, 0, HC_VARIANT_HC};
         best.ms = 1e30;
+        static const int hc_segs[4] = {64, 100, 132, 200};
+        static const int sparse_segs[4] = {512, 1024, 2048, 4096};   // the sparse tiles are larger
         for (size_t k = 0; k < std::min<size_t>(4, cs.size()) && st == HC_OK; ++k)
-            for (int seg : {64, 100, 132, 200}) {
+            for (int j = 0; j < 4; ++j) {
                 Cand c = cs[k];
-                c.segment = seg;
-                st = time_candidate(c, pats, np, d_y, n, d_out, cap, d_count, s, &c.ms);
+                c.segment = c.variant == HC_VARIANT_SPARSE ? sparse_segs[j] : hc_segs[j];
+                st = time_candidate(c, pats, np, d_y, n, d_out, cap, d_count, fl, s, &c.ms);
                 if (st != HC_OK) break;
                 if (c.ms < best.ms) best = c;
             }
@@ -149,11 +176,12 @@ extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *m
         t.w = best.w;
         t.schedule = best.schedule;
         t.segment = best.segment;
+        t.variant = best.variant;
         set_tuned(m, t);
         if (out) {
             out[i].m = m;
             out[i].params = hc_params{best.q, best.alpha, best.w};
-            out[i].launch = hc_launch{best.segment, best.schedule, HC_VARIANT_HC, 0};
+            out[i].launch = hc_launch{best.segment, best.schedule, best.variant, 0};
             out[i].gbps = double(n) / (best.ms * 1e-3) / 1e9;
         }
     }

@@ -281,11 +281,12 @@ __device__ __forceinline__ bool hc_segment(const uint32_t *__restrict__ t32, uin
 // that ends i + 1 steps further back and looks up its word, so 64 links are
 // checked per round; a ballot finds the first broken one. Returns the next
 // window end of the walk's window and marks it when it is a candidate.
-template <int Q, typename WT>
-__device__ __forceinline__ uint32_t hc_chain_wave(const uint32_t *__restrict__ t32, uint32_t tb,
-                                                  const WT *__restrict__ F, const PatternView &P,
-                                                  const Parked &pk, uint32_t lane,
-                                                  uint32_t *bitmap, uint32_t *any) {
+// The walk itself, with the q-gram hash at a tile-relative end supplied by
+// `hash` (text in LDS, or read in place from global memory).
+template <int Q, typename WT, typename H>
+__device__ __forceinline__ uint32_t chain_wave_impl(H hash, const WT *__restrict__ F, const PatternView &P,
+                                                    const Parked &pk, uint32_t lane, uint32_t *bitmap,
+                                                    uint32_t *any) {
     const uint32_t shift = P.m - Q + 1u;
     const int32_t lo = int32_t(pk.J) - int32_t(P.m) + 2 * Q;
     int32_t e = int32_t(pk.e);
@@ -300,7 +301,7 @@ __device__ __forceinline__ uint32_t hc_chain_wave(const uint32_t *__restrict__ t
         uint32_t vi = 0;
         WT zi = 0;
         if (valid) {
-            vi = qgram_hash<Q>(t32, tb + uint32_t(ei), P.s, P.mask);
+            vi = hash(uint32_t(ei));
             zi = F[vi];
         }
         // word of the q-gram after step i: step i - 1's word, or z for step 1
@@ -337,6 +338,15 @@ __device__ __forceinline__ uint32_t hc_chain_wave(const uint32_t *__restrict__ t
         }
         e -= 64 * Q;
     }
+}
+
+template <int Q, typename WT>
+__device__ __forceinline__ uint32_t hc_chain_wave(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                  const WT *__restrict__ F, const PatternView &P,
+                                                  const Parked &pk, uint32_t lane,
+                                                  uint32_t *bitmap, uint32_t *any) {
+    return chain_wave_impl<Q, WT>([&](uint32_t e) { return qgram_hash<Q>(t32, tb + e, P.s, P.mask); }, F, P, pk,
+                                  lane, bitmap, any);
 }
 
 // Wavefront schedule over window starts [slo, shi) (tile-relative): the 64
@@ -408,6 +418,75 @@ __device__ __forceinline__ void stage_commit(const Stage &st, uint8_t *lds_text)
         const uint32_t c = k * 256u + threadIdx.x;   // 256 threads per workgroup
         if (c < st.nch) dst[c] = st.r[k];
     }
+}
+
+// ----------------------------------------------------------------------------
+// Text read in place from global memory (the sparse variant): only the
+// aligned dwords that hold bytes of a hashed q-gram or of a verified window
+// are loaded. A dword that holds no byte of the text reads as 0 without a
+// load, so nothing outside the text's pages is touched.
+// ----------------------------------------------------------------------------
+typedef const __attribute__((address_space(1))) uint32_t global_u32;
+
+struct GlobalText {
+    uintptr_t lo, hi;   // the text's bytes are [lo, hi) (absolute addresses)
+};
+
+__device__ __forceinline__ uint32_t gdword(const GlobalText &T, uintptr_t d) {
+    return (d + 4u > T.lo && d < T.hi) ? *(global_u32 *)d : 0u;
+}
+
+// Hash (eq. (3)) of the q-gram that ends at absolute address e.
+template <int Q>
+__device__ __forceinline__ uint32_t ghash(const GlobalText &T, uintptr_t e, uint32_t s, uint32_t mask) {
+    uint32_t v = 0;
+    if constexpr (Q <= 4) {
+        const uintptr_t p = e - 3u, a = p & ~uintptr_t(3);
+        const uint32_t w = __builtin_amdgcn_alignbyte(gdword(T, a + 4u), gdword(T, a), uint32_t(p & 3u));
+#pragma unroll
+        for (int k = Q - 1; k >= 0; --k) v = (v << s) + __builtin_amdgcn_ubfe(w, 8 * (4 - Q + k), 8);
+    } else {
+        const uintptr_t p = e - 7u, a = p & ~uintptr_t(3);
+        const uint32_t sh = uint32_t(p & 3u);
+        const uint32_t d0 = gdword(T, a), d1 = gdword(T, a + 4u), d2 = gdword(T, a + 8u);
+        const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, sh);
+        const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, sh);
+#pragma unroll
+        for (int k = Q - 1; k >= 0; --k) {
+            const int b = 8 - Q + k;
+            const uint32_t c = b < 4 ? __builtin_amdgcn_ubfe(lo, 8 * b, 8) : __builtin_amdgcn_ubfe(hi, 8 * (b - 4), 8);
+            v = (v << s) + c;
+        }
+    }
+    return v & mask;
+}
+
+// Whether the m text bytes at absolute address a equal x (LDS, padded).
+__device__ __forceinline__ bool gwindow_equals(const GlobalText &T, uintptr_t a, const uint32_t *__restrict__ x32,
+                                               uint32_t m) {
+    const uint32_t sh = uint32_t(a & 3u);
+    const uintptr_t base = a & ~uintptr_t(3);
+    const uint32_t nw = (m + 3u) >> 2;
+    const uint32_t tail = (m & 3u) ? ((1u << (8u * (m & 3u))) - 1u) : 0xFFFFFFFFu;
+    uint32_t lo = gdword(T, base);
+    for (uint32_t i = 0; i < nw; ++i) {
+        const uint32_t hi = gdword(T, base + 4u * (i + 1u));
+        uint32_t d = __builtin_amdgcn_alignbyte(hi, lo, sh) ^ x32[i];
+        if (i + 1u == nw) d &= tail;
+        if (d) return false;
+        lo = hi;
+    }
+    return true;
+}
+
+// A parked chain walk finished by the whole wavefront with the q-grams read
+// in place; `base` is the absolute address of tile position 0.
+template <int Q, typename WT>
+__device__ __forceinline__ uint32_t gchain_wave(const GlobalText &T, uintptr_t base, const WT *__restrict__ F,
+                                                const PatternView &P, const Parked &pk, uint32_t lane,
+                                                uint32_t *bitmap, uint32_t *any) {
+    return chain_wave_impl<Q, WT>([&](uint32_t e) { return ghash<Q>(T, base + e, P.s, P.mask); }, F, P, pk, lane,
+                                  bitmap, any);
 }
 
 // Inclusive prefix sum across a wavefront with DPP row shifts and row

@@ -36,7 +36,7 @@ struct PatternData {
 // bucket (lengths in (2^(b-1), 2^b]); process-wide, last tuning wins.
 struct Tuned {
     bool set = false;
-    int q = 0, alpha = 0, w = 0, schedule = 0, segment = 0;
+    int q = 0, alpha = 0, w = 0, schedule = 0, segment = 0, variant = 0;
 };
 constexpr int kBuckets = 13;   // m up to 4096
 int m_bucket(int64_t m);

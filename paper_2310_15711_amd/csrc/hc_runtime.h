@@ -28,7 +28,7 @@ const DeviceInfo &device_info();
 struct Workspace {
     void *ctl = nullptr;          // control words (work tickets), zero-initialised
     uint32_t *counts = nullptr;   // tiles_cap entries
-    uint16_t *slots = nullptr;    // tiles_cap * 32 entries
+    uint32_t *slots = nullptr;    // tiles_cap * 32 entries
     uint32_t *spill = nullptr;    // spill_words_cap entries
     uint32_t tiles_cap = 0;
     uint64_t spill_words_cap = 0;

@@ -60,7 +60,7 @@ hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Works
             ws->tiles_cap = 0;
             const uint32_t cap = std::max<uint32_t>(tiles, 4096);
             if (hipMalloc(reinterpret_cast<void **>(&ws->counts), sizeof(uint32_t) * cap) != hipSuccess ||
-                hipMalloc(reinterpret_cast<void **>(&ws->slots), sizeof(uint16_t) * 32u * cap) != hipSuccess)
+                hipMalloc(reinterpret_cast<void **>(&ws->slots), sizeof(uint32_t) * 32u * cap) != hipSuccess)
                 return HC_ENOMEM;
             ws->tiles_cap = cap;
         }
@@ -116,7 +116,7 @@ hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req) {
     const Tuned t = get_tuned(p.m);
     if (lc.segment <= 0) lc.segment = t.set ? t.segment : 100;   // tile of 25600 starts
     if (lc.schedule == HC_SCHED_AUTO) lc.schedule = t.set ? t.schedule : HC_SCHED_SEGMENT;
-    if (lc.variant == HC_VARIANT_AUTO) lc.variant = HC_VARIANT_HC;
+    if (lc.variant == HC_VARIANT_AUTO) lc.variant = t.set && t.variant ? t.variant : HC_VARIANT_HC;
     (void)n;
     return lc;
 }

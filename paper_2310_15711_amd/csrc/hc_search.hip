@@ -42,7 +42,7 @@ struct SearchArgs {
     int64_t cap;
     int64_t *d_count;
     uint32_t *counts;    // per tile: occurrences
-    uint16_t *slots;     // per tile: up to kSlot tile-relative starts
+    uint32_t *slots;     // per tile: up to kSlot tile-relative starts
     uint32_t *spill;     // per tile: the occurrence bitmap, when denser
 };
 
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
                     while (b) {
                         const uint32_t bit = __builtin_ctz(b);
                         b &= b - 1u;
-                        A.slots[uint64_t(t) * kSlot + j++] = uint16_t(i * 32u + bit);
+                        A.slots[uint64_t(t) * kSlot + j++] = i * 32u + bit;
                     }
                 }
             } else {
@@ -169,6 +169,214 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
 
 }
 
+// Sparse variant for long patterns: no tile is staged. Every lane runs the
+// searching loop over its block of window starts and reads each q-gram it
+// hashes straight from global memory, so only the cache lines that hold
+// those q-grams are fetched (with shifts of m - q + 1 most lines of the text
+// are never read). Four attempts are fetched ahead, as in the segment
+// schedule. Candidates are marked in the LDS bitmap of the tile and compared
+// with x (also read in place); counts, slots and spilled bitmaps are written
+// exactly as the streaming kernel writes them, so the same emit kernel
+// follows.
+struct SparseLayout {
+    uint32_t bm_off, table_off, x_off, misc_off, total;
+};
+
+__host__ __device__ inline SparseLayout sparse_layout(uint32_t tile, uint32_t m, uint32_t table_bytes) {
+    SparseLayout L;
+    L.bm_off = 0;
+    L.table_off = align16(tile / 8u);
+    L.x_off = L.table_off + align16(table_bytes);
+    L.misc_off = L.x_off + align16(m) + 32u;
+    L.total = L.misc_off + 128u;
+    return L;
+}
+
+template <int Q, typename WT>
+__global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const SparseLayout L = sparse_layout(A.tile, A.m, A.table_bytes);
+    uint32_t *bm = reinterpret_cast<uint32_t *>(lds + L.bm_off);
+    WT *F = reinterpret_cast<WT *>(lds + L.table_off);
+    uint8_t *x8 = lds + L.x_off;
+    const uint32_t *x32 = reinterpret_cast<const uint32_t *>(x8);
+    uint32_t *misc = reinterpret_cast<uint32_t *>(lds + L.misc_off);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile_words = A.tile / 32u;
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.F);
+        uint4 *dst = reinterpret_cast<uint4 *>(F);
+        for (uint32_t i = tid; i < (A.table_bytes + 15u) / 16u; i += kBlock) dst[i] = src[i];
+        for (uint32_t i = tid; i < align16(A.m) + 32u; i += kBlock) x8[i] = i < A.m ? A.x[i] : 0;
+        for (uint32_t i = tid; i < tile_words; i += kBlock) bm[i] = 0u;
+        if (tid == 0) misc[8] = misc[9] = 0u;
+    }
+    __syncthreads();
+    const GlobalText T{reinterpret_cast<uintptr_t>(A.y), reinterpret_cast<uintptr_t>(A.y) + A.n};
+    const uint32_t shift = A.m - uint32_t(Q) + 1u;
+    const PatternView P{A.m, uint32_t(Q), A.s, A.mask, A.hv};
+    const uint32_t lane = tid & (kWave - 1);
+    uint32_t it = 0;
+    for (uint32_t t = blockIdx.x; t < A.n_tiles; t += gridDim.x) {
+        const uint64_t tile_lo = uint64_t(t) * A.tile;
+        const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
+        const uintptr_t base = T.lo + tile_lo;
+        uint32_t *any = &misc[8 + (it & 1u)];
+        const uint32_t lo = min(S, tid * A.seg), hi = min(S, lo + A.seg);
+        uint32_t J = lo + A.m - 1u;
+        const uint32_t Jend = hi + A.m - 1u;   // window ends of this lane: [J, Jend)
+        // A chain walk longer than kLocalSteps links is parked (state in e,
+        // v, z) and finished by the whole wavefront, 64 q-grams per round
+        // trip, instead of one dependent memory access per link.
+        bool parked = false;
+        uint32_t e = 0, v = 0;
+        WT z = 0;
+        while (__ballot(J < Jend) != 0ull) {   // wavefront-uniform
+            if (J < Jend && !parked) {
+                uint32_t vv[4];
+                WT zz[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t Jn = J + uint32_t(i) * shift;
+                    vv[i] = ghash<Q>(T, base + (Jn < Jend ? Jn : J), A.s, A.mask);
+                    zz[i] = F[vv[i]];
+                }
+                int first = 4;
+#pragma unroll
+                for (int i = 3; i >= 0; --i)
+                    if (zz[i] != 0 && J + uint32_t(i) * shift < Jend) first = i;
+                if (first == 4) {
+                    J += 4u * shift;   // four empty words in a row
+                } else {
+                    v = vv[0];
+                    z = zz[0];
+#pragma unroll
+                    for (int i = 1; i < 4; ++i)
+                        if (first == i) {
+                            v = vv[i];
+                            z = zz[i];
+                        }
+                    J += uint32_t(first) * shift;
+                    // chain walk towards the window start (as in the searching loop)
+                    const int32_t lo_e = int32_t(J) - int32_t(A.m) + 2 * Q;
+                    e = J;
+                    uint32_t next = J + 1u;
+                    bool broken = false;
+                    int steps = kLocalSteps;
+                    while (int32_t(e) >= lo_e) {
+                        if (steps-- == 0) {
+                            parked = true;
+                            break;
+                        }
+                        const uint32_t ep = e - Q;
+                        const uint32_t vp = ghash<Q>(T, base + ep, A.s, A.mask);
+                        if (!linked(z, vp)) {
+                            next = ep + shift;
+                            broken = true;
+                            break;
+                        }
+                        e = ep;
+                        v = vp;
+                        z = F[vp];
+                    }
+                    if (!parked) {
+                        if (!broken && v == A.hv) mark(bm, J + 1u - A.m, any);
+                        J = next;
+                    }
+                }
+            }
+            // parked walks of this wavefront, one at a time, all lanes
+            uint64_t pm = __ballot(parked);
+            while (pm) {
+                const int owner = __ffsll((unsigned long long)pm) - 1;
+                pm &= pm - 1ull;
+                Parked pk;
+                pk.J = uint32_t(__shfl((int)J, owner, kWave));
+                pk.e = uint32_t(__shfl((int)e, owner, kWave));
+                pk.v = uint32_t(__shfl((int)v, owner, kWave));
+                if constexpr (sizeof(WT) == 8) {
+                    const uint32_t zl = uint32_t(__shfl((int)uint32_t(z), owner, kWave));
+                    const uint32_t zh = uint32_t(__shfl((int)uint32_t(uint64_t(z) >> 32), owner, kWave));
+                    pk.z = (uint64_t(zh) << 32) | zl;
+                } else {
+                    pk.z = uint32_t(__shfl((int)uint32_t(z), owner, kWave));
+                }
+                const uint32_t next = gchain_wave<Q, WT>(T, base, F, P, pk, lane, bm, any);
+                if (lane == uint32_t(owner)) {
+                    J = next;
+                    parked = false;
+                }
+            }
+        }
+        lds_barrier();
+        const bool has = *any != 0u;
+        if (tid == 0) misc[8 + ((it + 1u) & 1u)] = 0u;
+        ++it;
+        uint32_t total = 0, mine = 0, w0 = 0, w1 = 0;
+        if (has) {
+            // verification, one candidate at a time per wavefront: the 64
+            // lanes compare 64 dwords of the window at once (loads in flight
+            // together instead of one dependent load per dword)
+            const uint32_t words = (S + 31u) / 32u;
+            const uint32_t wid = tid / kWave, nw = (A.m + 3u) >> 2;
+            const uint32_t tail = (A.m & 3u) ? ((1u << (8u * (A.m & 3u))) - 1u) : 0xFFFFFFFFu;
+            for (uint32_t i0 = wid * kWave; i0 < words; i0 += kBlock) {
+                const uint32_t i = i0 + lane;
+                uint32_t myw = i < words ? bm[i] : 0u;
+                uint64_t nz = __ballot(myw != 0u);
+                while (nz) {
+                    const int src = __ffsll((unsigned long long)nz) - 1;
+                    nz &= nz - 1ull;
+                    uint32_t b = uint32_t(__shfl((int)myw, src, kWave)), keep = b;
+                    while (b) {
+                        const uint32_t bit = __builtin_ctz(b);
+                        b &= b - 1u;
+                        const uintptr_t wa = base + (i0 + uint32_t(src)) * 32u + bit;
+                        const uint32_t sh = uint32_t(wa & 3u);
+                        const uintptr_t wb = wa & ~uintptr_t(3);
+                        bool diff = false;
+                        for (uint32_t k = lane; k < nw; k += kWave) {
+                            const uint32_t word = __builtin_amdgcn_alignbyte(gdword(T, wb + 4u * (k + 1u)),
+                                                                             gdword(T, wb + 4u * k), sh);
+                            uint32_t d = word ^ x32[k];
+                            if (k + 1u == nw) d &= tail;
+                            diff |= d != 0u;
+                        }
+                        if (__ballot(diff) != 0ull) keep &= ~(1u << bit);
+                    }
+                    if (lane == uint32_t(src)) myw = keep;
+                }
+                if (i < words) bm[i] = myw;
+            }
+            lds_barrier();
+            const uint32_t wpt = (words + kBlock - 1u) / kBlock;
+            w0 = min(words, tid * wpt);
+            w1 = min(words, w0 + wpt);
+            uint32_t c = 0;
+            for (uint32_t i = w0; i < w1; ++i) c += __popc(bm[i]);
+            mine = block_exclusive_scan(c, misc, &total);
+        }
+        if (tid == 0) A.counts[t] = total;
+        if (total != 0u) {
+            if (total <= kSlot) {
+                uint32_t j = mine;
+                for (uint32_t i = w0; i < w1; ++i) {
+                    uint32_t b = bm[i];
+                    while (b) {
+                        const uint32_t bit = __builtin_ctz(b);
+                        b &= b - 1u;
+                        A.slots[uint64_t(t) * kSlot + j++] = i * 32u + bit;
+                    }
+                }
+            } else {
+                for (uint32_t i = w0; i < w1; ++i) A.spill[uint64_t(t) * tile_words + i] = bm[i];
+            }
+            for (uint32_t i = w0; i < w1; ++i) bm[i] = 0u;
+        }
+        lds_barrier();   // the bitmap is clear before the next tile marks
+    }
+}
+
 // Ordered output: workgroup b writes the occurrences of tiles
 // [b * per, (b + 1) * per) in tile order. Its offset is the sum of the counts
 // of all earlier tiles, read in parallel; the search kernel has finished, so
@@ -177,7 +385,7 @@ struct EmitArgs {
     uint32_t n_tiles, tile, per;
     uint64_t starts;
     const uint32_t *counts;
-    const uint16_t *slots;
+    const uint32_t *slots;
     const uint32_t *spill;
     int64_t *out;
     int64_t cap;
@@ -326,6 +534,89 @@ static int occupancy(KernelFn fn, uint32_t lds_bytes) {
     return nb;
 }
 
+template <int Q>
+static KernelFn pick_sparse_w(int w) {
+    switch (w) {
+        case 8: return hc_sparse_kernel<Q, uint8_t>;
+        case 16: return hc_sparse_kernel<Q, uint16_t>;
+        case 32: return hc_sparse_kernel<Q, uint32_t>;
+        default: return hc_sparse_kernel<Q, uint64_t>;
+    }
+}
+
+static KernelFn pick_sparse(int q, int w) {
+    switch (q) {
+        case 1: return pick_sparse_w<1>(w);
+        case 2: return pick_sparse_w<2>(w);
+        case 3: return pick_sparse_w<3>(w);
+        case 4: return pick_sparse_w<4>(w);
+        case 5: return pick_sparse_w<5>(w);
+        case 6: return pick_sparse_w<6>(w);
+        case 7: return pick_sparse_w<7>(w);
+        default: return pick_sparse_w<8>(w);
+    }
+}
+
+static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const Workspace *ws,
+                             int64_t *d_out, int64_t cap, int64_t *d_count, hipStream_t stream);
+
+// Sparse variant: tiles of 256 * segment window starts (segment 0 = 1024),
+// no text staging; the same emit kernel as the streaming path.
+static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
+                               int64_t *d_out, int64_t cap, int64_t *d_count, const hc_launch &lc,
+                               hipStream_t stream) {
+    const PatternData &pd = p->data;
+    const DeviceInfo &di = device_info();
+    const uint32_t m = uint32_t(pd.m);
+    const uint32_t table_bytes = uint32_t(pd.F.size() * (pd.w / 8));
+    const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
+    uint32_t seg = lc.segment > 0 ? std::min<uint32_t>(uint32_t(lc.segment), 4096u) : 1024u;
+    seg = std::max<uint32_t>(seg, 32u);
+    SparseLayout L = sparse_layout(kBlock * seg, m, table_bytes);
+    while (L.total > di.max_lds_per_block && seg > 32) {
+        seg /= 2;
+        L = sparse_layout(kBlock * seg, m, table_bytes);
+    }
+    if (L.total > di.max_lds_per_block) return HC_EINVAL;
+    const uint32_t tile = kBlock * seg;
+    const uint64_t n_tiles64 = (starts + tile - 1) / tile;
+    if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
+    const uint32_t n_tiles = uint32_t(n_tiles64);
+    Workspace *ws = nullptr;
+    hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
+    if (st != HC_OK) return st;
+    KernelFn fn = pick_sparse(pd.q, pd.w);
+    int per_cu = occupancy(fn, L.total);
+    if (lc.wg_per_cu > 0) per_cu = std::min(per_cu, int(lc.wg_per_cu));
+    const uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, int64_t(di.cus) * per_cu)));
+    SearchArgs A;
+    A.y = d_y;
+    A.n = uint64_t(n);
+    A.x = dc.d_x;
+    A.F = dc.d_F;
+    A.m = m;
+    A.q = uint32_t(pd.q);
+    A.s = uint32_t(pd.s);
+    A.mask = pd.mask;
+    A.hv = pd.hv;
+    A.table_bytes = table_bytes;
+    A.tile = tile;
+    A.seg = seg;
+    A.starts = starts;
+    A.n_tiles = n_tiles;
+    A.out = d_out;
+    A.cap = cap;
+    A.d_count = d_count;
+    A.counts = ws->counts;
+    A.slots = ws->slots;
+    A.spill = ws->spill;
+    if (n_tiles > 0) {
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
+        if (hipGetLastError() != hipSuccess) return HC_EHIP;
+    }
+    return launch_emit(n_tiles, tile, starts, ws, d_out, cap, d_count, stream);
+}
+
 hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
                         int64_t *d_out, int64_t cap, int64_t *d_count, const hc_launch &lc,
                         hipStream_t stream) {
@@ -335,7 +626,8 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     const uint32_t table_bytes = uint32_t(pd.F.size() * (pd.w / 8));
     const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
 
-    uint32_t seg = std::min<uint32_t>(uint32_t(lc.segment), 256u);   // tile-relative starts fit 16 bits
+    if (lc.variant == HC_VARIANT_SPARSE) return launch_sparse(p, dc, d_y, n, d_out, cap, d_count, lc, stream);
+    uint32_t seg = std::min<uint32_t>(uint32_t(lc.segment), 256u);
     LdsLayout L = lds_layout(kBlock * seg, m, table_bytes, 0);
     while (L.total > di.max_lds_per_block && seg > 8) {
         seg = std::max<uint32_t>(8, seg / 2);
@@ -389,13 +681,19 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
     if (hipGetLastError() != hipSuccess) return HC_EHIP;
 
+    return launch_emit(n_tiles, tile, starts, ws, d_out, cap, d_count, stream);
+}
+
+static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const Workspace *ws,
+                             int64_t *d_out, int64_t cap, int64_t *d_count, hipStream_t stream) {
+    const DeviceInfo &di = device_info();
     EmitArgs E;
     E.n_tiles = n_tiles;
     E.tile = tile;
     // at most 256 tiles per workgroup of the ordered output
     const uint32_t emit_grid = std::max<uint32_t>(
         std::max<uint32_t>(1, (n_tiles + kBlock - 1) / kBlock),
-        std::min<uint32_t>(n_tiles, uint32_t(di.cus) * 2u));
+        std::min<uint32_t>(std::max<uint32_t>(n_tiles, 1), uint32_t(di.cus) * 2u));
     E.per = (n_tiles + emit_grid - 1) / emit_grid;
     E.starts = starts;
     E.counts = ws->counts;

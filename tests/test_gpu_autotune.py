@@ -28,7 +28,7 @@ def text():
 
 def test_autotune_choices_are_used_and_exact(text):
     y, yd = text
-    lengths = [2, 4, 8, 32, 300]
+    lengths = [2, 4, 8, 32, 300, 1024]
     announce("autotune", lengths)
     try:
         tuned = B.hc_autotune(yd, lengths, patterns=3)
@@ -38,7 +38,11 @@ def test_autotune_choices_are_used_and_exact(text):
             seg, sched, variant, wg = t["launch"]
             assert 1 <= q <= min(t["m"], 8)
             assert (alpha, w) in {(8, 8), (10, 16), (11, 16), (12, 16), (12, 32)}
-            assert sched in (B.HC_SCHED_SEGMENT, B.HC_SCHED_DENSE) and seg in (64, 100, 132, 200)
+            if variant == B.HC_VARIANT_SPARSE:
+                assert t["m"] >= 256 and sched == B.HC_SCHED_SEGMENT and seg in (512, 1024, 2048, 4096)
+            else:
+                assert variant == B.HC_VARIANT_HC
+                assert sched in (B.HC_SCHED_SEGMENT, B.HC_SCHED_DENSE) and seg in (64, 100, 132, 200)
             assert t["gbps"] > 0
         rs = np.random.default_rng(3)
         for t in tuned:
