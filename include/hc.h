@@ -75,13 +75,15 @@ enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENS
  *   hc        the plain searching phase (Section 3.3);
  *   sentinel  SHC (Section 3.4, third optimisation): a copy of x is placed
  *             after each text tile in on-chip memory, so the loop over
- *             empty words runs without a position test;
+ *             empty words runs without a position test (a lane's loop may
+ *             run into the next lane's range before it stops);
  *   sparse    for long patterns: no tile is staged; each lane reads the
  *             q-grams it hashes (and the windows it verifies) in place, so
  *             only the cache lines that hold them are fetched; long chain
  *             walks and verifications are shared by a whole wavefront.
  *             Tiles hold 256 * segment window starts (segment 0 = 1024, up
- *             to 4096). The sentinel variant is accepted and runs as hc. */
+ *             to 4096).
+ * The sentinel variant ignores the schedule (one range per lane). */
 enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIANT_SPARSE = 3 };
 
 /* Launch shape of the search kernel. A field set to 0 is chosen by the

@@ -617,6 +617,45 @@ __device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t
     return verify_tile(t32, tb, x32, P, S, bm, misc, it);
 }
 
+// SHC (Section 3.4, third optimisation) on a tile: a copy of x sits right
+// after the tile's staged bytes (the sentinel), so the loop over empty words
+// needs no position test: it always stops at a non-empty word, at the latest
+// inside the copy of x, whose q-grams all have non-empty words and which is
+// longer than one shift. A lane's loop may thus run past its own range; the
+// window it stops at is then simply not searched by this lane.
+template <int Q, typename WT>
+__device__ __forceinline__ void shc_lane(const uint32_t *__restrict__ t32, uint32_t tb, const WT *__restrict__ F,
+                                         const PatternView &P, uint32_t J, uint32_t Jend, uint32_t *bitmap,
+                                         uint32_t *any) {
+    const uint32_t shift = P.m - Q + 1u;
+    while (J < Jend) {
+        uint32_t v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
+        WT z = F[v];
+        while (z == 0) {   // no bounds test: the sentinel ends this loop
+            J += shift;
+            v = qgram_hash<Q>(t32, tb + J, P.s, P.mask);
+            z = F[v];
+        }
+        if (J >= Jend) break;
+        uint32_t e = J;
+        bool hit = false;
+        const uint32_t next = hc_chain<Q, WT>(t32, tb, F, P, J, e, v, z, 1 << 30, &hit);
+        if (hit) mark(bitmap, J + 1u - P.m, any);
+        J = next;
+    }
+}
+
+template <int Q, typename WT>
+__device__ __forceinline__ TileResult shc_tile(const uint32_t *__restrict__ t32, uint32_t tb,
+                                               const WT *__restrict__ F, const uint32_t *__restrict__ x32,
+                                               const PatternView &P, uint32_t S, uint32_t seg, uint32_t *bm,
+                                               uint32_t *misc, uint32_t &it) {
+    const uint32_t lo = min(S, threadIdx.x * seg), hi = min(S, lo + seg);
+    shc_lane<Q, WT>(t32, tb, F, P, lo + P.m - 1u, hi + P.m - 1u, bm, &misc[8 + (it & 1u)]);
+    lds_barrier();
+    return verify_tile(t32, tb, x32, P, S, bm, misc, it);
+}
+
 // Dense schedule: the test of the searching loop (first word nonzero, each
 // q-gram of the chain linked to the next, last hash equal to H_v), applied to
 // every window of the tile rather than only to the windows the shifts land

@@ -27,6 +27,9 @@ namespace hc {
 // Positions a tile keeps in its slot; denser tiles store their bitmap.
 constexpr uint32_t kSlot = 32;
 
+// Internal schedule code of the SHC (sentinel) variant.
+constexpr int kSchedShc = 16;
+
 struct SearchArgs {
     const uint8_t *y;
     uint64_t n;
@@ -49,7 +52,7 @@ struct SearchArgs {
 template <int Q, typename WT, int SCHED, int K>
 __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const LdsLayout L = lds_layout(A.tile, A.m, A.table_bytes, 0);
+    const LdsLayout L = lds_layout(A.tile, A.m, A.table_bytes, SCHED == kSchedShc ? A.m : 0u);
     uint8_t *t8 = lds + L.text_off;
     const uint32_t *t32 = reinterpret_cast<const uint32_t *>(t8);
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds + L.bitmap_off);
@@ -96,6 +99,11 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
         const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
         stage_commit(stage, t8);
         lds_barrier();
+        if constexpr (SCHED == kSchedShc) {
+            // the sentinel: a copy of x right after the tile's last window
+            for (uint32_t i = tid; i < A.m; i += kBlock) t8[tb + S + A.m - 1u + i] = x8[i];
+            lds_barrier();
+        }
 
         // the next tile's bytes travel while this one is searched
         const uint32_t tb_cur = tb;
@@ -133,6 +141,12 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
                 }
                 mine = block_exclusive_scan(c, misc, &total);
             }
+        } else if constexpr (SCHED == kSchedShc) {
+            const TileResult R = shc_tile<Q, WT>(t32, tb_cur, F, x32, P, S, A.seg, bm, misc, it);
+            total = R.total;
+            mine = R.mine;
+            w0 = R.w0;
+            w1 = R.w1;
         } else if constexpr (SCHED >= HC_SCHED_DENSE) {   // dense, C = SCHED - HC_SCHED_DENSE
             const TileResult R = dense_tile<(Q <= 4 ? Q : 4), WT, (SCHED - HC_SCHED_DENSE)>(
                 t32, tb_cur, F, x32, P, S, bm, misc, it);
@@ -484,6 +498,7 @@ static int lookahead_for(uint32_t shift) { return shift <= 12 ? 4 : 1; }
 template <int Q, typename WT>
 static KernelFn pick_sched(int sched, int K) {
     if (sched == HC_SCHED_WAVE) return hc_search_kernel<Q, WT, HC_SCHED_WAVE, 1>;
+    if (sched == kSchedShc) return hc_search_kernel<Q, WT, kSchedShc, 1>;
     if constexpr (Q <= 4) {
         // dense: one instance per number of links per window (0..3)
         if (sched == HC_SCHED_DENSE + 0) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 0, 1>;
@@ -627,15 +642,17 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
 
     if (lc.variant == HC_VARIANT_SPARSE) return launch_sparse(p, dc, d_y, n, d_out, cap, d_count, lc, stream);
+    const bool shc = lc.variant == HC_VARIANT_SENTINEL;
+    const uint32_t extra = shc ? m : 0u;   // room for the sentinel copy of x
     uint32_t seg = std::min<uint32_t>(uint32_t(lc.segment), 256u);
-    LdsLayout L = lds_layout(kBlock * seg, m, table_bytes, 0);
+    LdsLayout L = lds_layout(kBlock * seg, m, table_bytes, extra);
     while (L.total > di.max_lds_per_block && seg > 8) {
         seg = std::max<uint32_t>(8, seg / 2);
-        L = lds_layout(kBlock * seg, m, table_bytes, 0);
+        L = lds_layout(kBlock * seg, m, table_bytes, extra);
     }
     while (kBlock * seg + m - 1u > stage_limit(kBlock) && seg > 8) seg -= 4;
     if (L.total > di.max_lds_per_block || kBlock * seg + m - 1u > stage_limit(kBlock)) return HC_EINVAL;
-    L = lds_layout(kBlock * seg, m, table_bytes, 0);
+    L = lds_layout(kBlock * seg, m, table_bytes, extra);
     const uint32_t tile = kBlock * seg;
     const uint64_t n_tiles64 = (starts + tile - 1) / tile;
     if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
@@ -647,7 +664,7 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
 
     // the dense schedule is instantiated for q <= 4 and up to 3 links per
     // window; other patterns run the searching loop
-    int sched = lc.schedule;
+    int sched = shc ? kSchedShc : lc.schedule;
     if (sched == HC_SCHED_DENSE) {
         const int links = int(m) / pd.q - 1;
         sched = (pd.q <= 4 && links <= 3) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;

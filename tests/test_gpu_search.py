@@ -241,10 +241,11 @@ def test_full_size_sampled(torch_dev, sigma):
     torch.cuda.empty_cache()
 
 
-def test_sparse_variant_against_oracle(torch_dev):
-    """The sparse variant (text read in place, no staging) on random cases,
-    closed forms and misaligned views."""
-    g = random.Random(77)
+@pytest.mark.parametrize("variant", [B.HC_VARIANT_SPARSE, B.HC_VARIANT_SENTINEL])
+def test_variants_against_oracle(torch_dev, variant):
+    """The sparse variant (text read in place, no staging) and the sentinel
+    variant (SHC) on random cases, closed forms and misaligned views."""
+    g = random.Random(77 + variant)
     for case in range(120):
         sigma = g.choice([2, 4, 20, 256])
         n = g.choice([g.randint(0, 5000), g.randint(5000, 400000)])
@@ -265,29 +266,30 @@ def test_sparse_variant_against_oracle(torch_dev):
         alpha = g.randint(1, {8: 16, 16: 15, 32: 14, 64: 13}[w])
         seg = g.choice([0, 32, 100, 1024, 4096])
         off = g.randint(0, 3)
-        announce("sparse", case, f"n={n} m={m} sigma={sigma} q={q} a={alpha} w={w} seg={seg} off={off}")
+        announce("variant", variant, case, f"n={n} m={m} sigma={sigma} q={q} a={alpha} w={w} seg={seg} off={off}")
         buf = to_dev(np.concatenate([np.zeros(off, np.uint8), y]), torch_dev)
         yd = buf[off:]
-        got, c = gpu_occ(x, yd, (q, alpha, w), (seg, 0, B.HC_VARIANT_SPARSE, 0))
+        got, c = gpu_occ(x, yd, (q, alpha, w), (seg, 0, variant, 0))
         want = O.occurrences(x, y)
         assert c == len(want)
         assert np.array_equal(got, want), (case, n, m, q, alpha, w, seg)
     n = 60_000
     yd = to_dev(np.full(n, ord("a"), dtype=np.uint8), torch_dev)
     for m in (1, 9, 300):
-        announce("sparse a^n", m)
-        got, c = gpu_occ(b"a" * m, yd, (min(m, 4), 10, 32), (64, 0, B.HC_VARIANT_SPARSE, 0))
+        announce("variant a^n", variant, m)
+        got, c = gpu_occ(b"a" * m, yd, (min(m, 4), 10, 32), (64, 0, variant, 0))
         assert c == n - m + 1 and np.array_equal(got, np.arange(n - m + 1))
 
 
 @pytest.mark.parametrize("sigma", [4, 64])
-def test_sparse_full_size(torch_dev, sigma):
+def test_variants_full_size(torch_dev, sigma):
     y = W.single_text(sigma)
     yd = to_dev(y, torch_dev)
-    for m in (64, 256, 1024):
-        for off, x in W.single_patterns(y, sigma, m, count=2):
-            announce("sparse full", sigma, m, off)
-            want = O.occurrences(x, y)
-            got, c = gpu_occ(x, yd, None, (0, 0, B.HC_VARIANT_SPARSE, 0), cap=int(want.size) + 16)
-            assert c == want.size and np.array_equal(got, want)
+    for variant, lengths in ((B.HC_VARIANT_SPARSE, (64, 256, 1024)), (B.HC_VARIANT_SENTINEL, (4, 32, 1024))):
+        for m in lengths:
+            for off, x in W.single_patterns(y, sigma, m, count=2):
+                announce("variant full", variant, sigma, m, off)
+                want = O.occurrences(x, y)
+                got, c = gpu_occ(x, yd, None, (0, 0, variant, 0), cap=int(want.size) + 16)
+                assert c == want.size and np.array_equal(got, want)
     del yd
