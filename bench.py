@@ -401,12 +401,38 @@ def run_served(args):
             "checked_vs_alone": int(sample.size), "same_as_alone": same,
         }
         log(f"served rate {rate:.0f}/s: {out[str(int(rate))]}")
-    del dtexts
+    # baseline: the same kind of requests, one hc_search_async launch each,
+    # back to back on one stream (GPU-busy time counted from HIP events)
+    reqs = W.request_stream(texts, 1000.0, 2.0, sub=99)
+    handles = [B.hc_preprocess(r.pattern) for r in reqs]
+    pos = torch.empty(1 << 24, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(len(reqs), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    for i in range(min(8, len(reqs))):   # warm-up
+        B.hc_search_async(handles[i], dtexts[reqs[i].text], pos, cnt[i:i + 1], stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in reqs]
+    w0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        ev[i][0].record(stream)
+        B.hc_search_async(handles[i], dtexts[r.text], pos, cnt[i:i + 1], stream=stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    busy = sum(a.elapsed_time(b) for a, b in ev) * 1e-3
+    nbytes = float(sum(texts[r.text].size for r in reqs))
+    baseline = {"requests": len(reqs), "gbps_gpu_busy": round(nbytes / busy / 1e9, 1),
+                "gbps_wall": round(nbytes / wall / 1e9, 1)}
+    log(f"served baseline (one launch per request): {baseline}")
+    del dtexts, pos
     torch.cuda.empty_cache()
+    best = max(out.values(), key=lambda r: r["agg_gbps"])
     return {"workload": f"served HC: {len(texts)} resident texts x {args.serve_text_mib} MiB "
                         f"(4 iid bytes, 4 order-2 Markov), Poisson arrivals for "
                         f"{args.serve_seconds} s per rate, m log-uniform 4..2048",
-            "budget_mib": args.serve_budget_mib, "rates": out}
+            "budget_mib": args.serve_budget_mib, "rates": out,
+            "per_request_launches": baseline,
+            "speedup_vs_per_request_gpu_busy": round(best["agg_gbps"] / baseline["gbps_gpu_busy"], 2)}
 
 
 def main():

@@ -105,6 +105,10 @@ hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pai
 // After a run reported scratch overflow: room for `total` positions.
 hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total);
 
+// Copies n staged (table, padded bytes) entries into pool slots d_slots[i].
+hc_status scatter_patterns(const uint8_t *d_src, const uint32_t *d_slots, uint32_t n, uint32_t table_bytes,
+                           uint32_t x_stride, uint8_t *Fpool, uint8_t *xpool, hipStream_t s);
+
 constexpr uint32_t kBatchGroup = 128;   // patterns searched per staged tile
 
 }  // namespace hc

@@ -376,6 +376,21 @@ __global__ __launch_bounds__(256) void hc_pair_emit(const uint64_t *pair_base, u
     }
 }
 
+// Copies n staged patterns into their pool slots: entry i (stride
+// table_bytes + x_stride bytes, both multiples of 16) holds a table and the
+// padded pattern bytes of slot slots[i]. One workgroup per entry.
+__global__ __launch_bounds__(256) void hc_scatter_patterns(const uint8_t *src, const uint32_t *slots, uint32_t n,
+                                                           uint32_t table_bytes, uint32_t x_stride, uint8_t *Fpool,
+                                                           uint8_t *xpool) {
+    const uint32_t i = blockIdx.x;
+    if (i >= n) return;
+    const uint4 *e = reinterpret_cast<const uint4 *>(src + uint64_t(i) * (table_bytes + x_stride));
+    uint4 *f = reinterpret_cast<uint4 *>(Fpool + uint64_t(slots[i]) * table_bytes);
+    uint4 *x = reinterpret_cast<uint4 *>(xpool + uint64_t(slots[i]) * x_stride);
+    for (uint32_t k = threadIdx.x; k < table_bytes / 16u; k += blockDim.x) f[k] = e[k];
+    for (uint32_t k = threadIdx.x; k < x_stride / 16u; k += blockDim.x) x[k] = e[table_bytes / 16u + k];
+}
+
 __global__ void hc_batch_reset(unsigned long long *ctl) {
     if (threadIdx.x < 4) ctl[threadIdx.x] = 0ull;
 }
@@ -662,6 +677,15 @@ hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pai
     return D.last_error == hipSuccess ? HC_OK : HC_EHIP;
 }
 
+hc_status scatter_patterns(const uint8_t *d_src, const uint32_t *d_slots, uint32_t n, uint32_t table_bytes,
+                           uint32_t x_stride, uint8_t *Fpool, uint8_t *xpool, hipStream_t s) {
+    if (n == 0) return HC_OK;
+    if (table_bytes % 16u || x_stride % 16u) return HC_EINVAL;
+    hipLaunchKernelGGL(hc_scatter_patterns, dim3(n), dim3(256), 0, s, d_src, d_slots, n, table_bytes, x_stride,
+                       Fpool, xpool);
+    return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
+}
+
 hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total) {
     // A workgroup reserves a new chunk of max(kChunk, c) when the c positions
     // of a (pair, tile) do not fit in what is left of its chunk; that rest
@@ -770,7 +794,7 @@ hc_status hc_batch_plan_run(hc_batch_plan *P, int64_t *d_pos, int64_t cap, int64
     if (!P || !total || !d_pair_off || cap < 0 || (cap > 0 && !d_pos)) return HC_EINVAL;
     *total = 0;
     hipStream_t s = hipStream_t(stream);
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
         // (re)build the graph for these buffers
         if (!P->exec || P->g_pos != d_pos || P->g_off != d_pair_off || P->g_cap != cap || P->g_stream != s) {
             P->drop_graph();

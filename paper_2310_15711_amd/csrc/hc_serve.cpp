@@ -104,6 +104,7 @@ struct hc_server {
     std::thread worker;
 
     ~hc_server() {
+        if (h_up) (void)hipHostFree(h_up);
         if (h_pos) (void)hipHostFree(h_pos);
         if (h_off) (void)hipHostFree(h_off);
         if (h_ctl) (void)hipHostFree(h_ctl);
@@ -153,8 +154,45 @@ struct hc_server {
     }
 
     hc_status step(std::vector<std::shared_ptr<Request>> &members, uint64_t &bytes);
+    hc_status upload(const std::vector<std::shared_ptr<Request>> &reqs);
+
+    // staging of newly admitted patterns: one copy and one scatter per step
+    uint8_t *h_up = nullptr;   // pinned
+    size_t h_up_cap = 0;
+    DeviceBuf d_up, d_up_slots;
     void run();
 };
+
+// Tables and bytes of newly admitted requests into their slots: packed in
+// pinned memory, copied once, scattered by one kernel. The step that follows
+// synchronises the stream before the staging buffer is reused.
+hc_status hc_server::upload(const std::vector<std::shared_ptr<Request>> &reqs) {
+    const size_t entry = size_t(table_bytes) + kXStride, need = entry * reqs.size();
+    if (h_up_cap < need) {
+        if (h_up) (void)hipHostFree(h_up);
+        h_up = nullptr;
+        h_up_cap = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&h_up), need, hipHostMallocDefault) != hipSuccess)
+            return HC_ENOMEM;
+        h_up_cap = need;
+    }
+    std::vector<uint32_t> slot(reqs.size());
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        uint8_t *e = h_up + i * entry;
+        std::memcpy(e, reqs[i]->F.data(), table_bytes);
+        std::memset(e + table_bytes, 0, kXStride);
+        std::memcpy(e + table_bytes, reqs[i]->x.data(), reqs[i]->x.size());
+        slot[i] = uint32_t(reqs[i]->slot);
+    }
+    if (d_up.ensure(need) != HC_OK) return HC_ENOMEM;
+    if (hipMemcpyAsync(d_up.p, h_up, need, hipMemcpyHostToDevice, stream) != hipSuccess) return HC_EHIP;
+    hc_status st = d_up_slots.upload(slot.data(), slot.size() * 4, stream);
+    if (st != HC_OK) return st;
+    // the slot list is pageable: wait for its copy before the vector goes
+    if (hipStreamSynchronize(stream) != hipSuccess) return HC_EHIP;
+    return scatter_patterns(d_up.as<uint8_t>(), d_up_slots.as<uint32_t>(), uint32_t(reqs.size()), table_bytes,
+                            kXStride, Fpool.as<uint8_t>(), xpool.as<uint8_t>(), stream);
+}
 
 // One step: the current chunk of every text with active requests, for all
 // of them (`members`, in pair order); their positions are appended.
@@ -212,8 +250,10 @@ hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64
     int64_t cap = int64_t(np * kResultReserve);
     if (d_pos.bytes / 8 > size_t(cap)) cap = int64_t(d_pos.bytes / 8);
     if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
-    // a second run, with room for everything the first one counted, always fits
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    // a second run, with room for everything the first one counted, fits;
+    // two more runs are allowed before the step fails
+    unsigned long long reserved_first = 0;
+    for (int attempt = 0; attempt < 4; ++attempt) {
         if ((st = batch_enqueue(D, d_pos.as<int64_t>(), cap, d_off.as<int64_t>(), stream)) != HC_OK)
             return fail("launch", st);
         if (hipMemcpyAsync(h_ctl, D.ctl.p, 4 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -228,9 +268,14 @@ hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64
             if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
         }
         if (short_scratch || short_out) {
-            if (attempt == 1)
-                std::fprintf(stderr, "hc_serve: second run short (scratch %d, out %d, total %llu, cap %lld)\n",
-                             int(short_scratch), int(short_out), (unsigned long long)total, (long long)cap);
+            if (attempt >= 1)
+                std::fprintf(stderr,
+                             "hc_serve: second run short (scratch %d, out %d, total %llu, cap %lld, reserved %llu "
+                             "then %llu, scratch %llu, grid %u, items %u, entries %llu)\n",
+                             int(short_scratch), int(short_out), (unsigned long long)total, (long long)cap,
+                             reserved_first, h_ctl[1], (unsigned long long)D.scratch_cap, D.grid, D.n_items,
+                             (unsigned long long)D.n_entries);
+            reserved_first = h_ctl[1];
             continue;
         }
         if (pinned(h_pos, h_pos_cap, total) != HC_OK) return fail("host positions", HC_ENOMEM);
@@ -279,15 +324,7 @@ void hc_server::run() {
         }
         const auto t0 = Clock::now();
         hc_status st = HC_OK;
-        for (auto &r : uploads) {
-            if (hipMemcpyAsync(Fpool.as<uint8_t>() + size_t(r->slot) * table_bytes, r->F.data(), table_bytes,
-                               hipMemcpyHostToDevice, stream) != hipSuccess ||
-                hipMemcpyAsync(xpool.as<uint8_t>() + size_t(r->slot) * kXStride, r->x.data(), r->x.size(),
-                               hipMemcpyHostToDevice, stream) != hipSuccess) {
-                std::fprintf(stderr, "hc_serve: pattern upload failed: %s\n", hipGetErrorString(hipGetLastError()));
-                st = HC_EHIP;
-            }
-        }
+        if (!uploads.empty()) st = upload(uploads);
         uint64_t bytes = 0;
         if (st == HC_OK) st = step(members, bytes);
         const double dt = std::chrono::duration<double>(Clock::now() - t0).count();
