@@ -699,9 +699,57 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
         uint32_t w[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+        uint32_t bits = 0;
+        if constexpr (C == 0) {
+            // the 8 window-end hashes two at a time in 16-bit lanes: column
+            // k holds byte k of every window's q-gram (8 consecutive text
+            // bytes), zero-extended in pairs; shifts and sums wrap mod 2^16,
+            // which 2^alpha divides (alpha <= 16)
+            typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+            u16x2 acc[4];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                constexpr int o0 = 4 - Q;   // offset of column 0 from p0
+                const int o = o0 + k;
+                const uint32_t lo = o ? __builtin_amdgcn_alignbyte(w[1], w[0], o) : w[0];
+                const uint32_t hi = o ? __builtin_amdgcn_alignbyte(w[2], w[1], o) : w[1];
+                const uint32_t pr[4] = {__builtin_amdgcn_perm(0u, lo, 0x0C010C00u),
+                                        __builtin_amdgcn_perm(0u, lo, 0x0C030C02u),
+                                        __builtin_amdgcn_perm(0u, hi, 0x0C010C00u),
+                                        __builtin_amdgcn_perm(0u, hi, 0x0C030C02u)};
+                const uint16_t sk = uint16_t(P.s * uint32_t(k));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const u16x2 r = __builtin_bit_cast(u16x2, pr[i]);
+                    acc[i] = k == 0 ? r : acc[i] + (r << u16x2{sk, sk});
+                }
+            }
+            const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
+            uint32_t any = 0, dd[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                dd[i] = (__builtin_bit_cast(uint32_t, acc[i]) & mask2) ^ hv2;   // zero half: H = H_v
+                any |= (dd[i] - 0x00010001u) & ~dd[i] & 0x80008000u;
+            }
+            if (any) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    bits |= (uint32_t((dd[i] & 0xFFFFu) == 0u) | (uint32_t((dd[i] >> 16) == 0u) << 1)) << (2 * i);
+                if (inline_check) {   // the window is in the word that ends it
+                    uint32_t eq = 0;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
+                                                      : w[j >> 2];
+                        eq |= uint32_t((word & xmask) == xw) << j;
+                    }
+                    bits &= eq;
+                }
+            }
+        }
         uint32_t h[E], wend[8];
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+        for (int j = 0; j < E && C > 0; ++j) {
             // bytes a0 + j - 3 .. a0 + j
             const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
                                           : w[j >> 2];
@@ -711,11 +759,7 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
             for (int k = Q - 1; k >= 0; --k) v = (v << P.s) + __builtin_amdgcn_ubfe(word, 8 * (4 - Q + k), 8);
             h[j] = v & P.mask;
         }
-        uint32_t bits = 0;
-        if constexpr (C == 0) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) bits |= uint32_t(h[j] == P.hv) << j;
-        } else {
+        if constexpr (C > 0) {
             WT z[E - Z0];
 #pragma unroll
             for (int j = Z0; j < E; ++j) z[j - Z0] = F[h[j]];
@@ -729,7 +773,7 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
                 bits |= uint32_t(alive) << j;
             }
         }
-        if (inline_check) {
+        if (C > 0 && inline_check) {
             uint32_t eq = 0;
 #pragma unroll
             for (int j = 0; j < 8; ++j) eq |= uint32_t((wend[j] & xmask) == xw) << j;
