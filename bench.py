@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--load-tuned", default=None,
                     help="use the choices in this JSON file instead of tuning (profiling runs)")
     ap.add_argument("--lds-dir", default=None, help="with --summarize: rocprofv3 LDS counter pass")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_DIR", "NAME", "TITLE"),
+                    help="write profiles/NAME.md: the kernel table of a rocprofv3 --stats run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-patterns", type=int, default=12,
                     help="oracle sample: patterns per (sigma, m)")
@@ -134,6 +136,20 @@ def _counter_per_dispatch(d, counter, name_part):
         if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
             per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
     return (sum(per.values()) / len(per)) if per else None, len(per)
+
+
+def summarize_stats(stats_dir, name, title, cmd):
+    """Kernel table of one rocprofv3 --kernel-trace --stats run."""
+    stats = _read_csv(_find(stats_dir, "kernel_stats.csv"))
+    lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command(s):", "", "```", cmd.strip(), "```", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for r in stats:
+        short = r["Name"].split("(")[0].replace("void ", "")[:90]
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
+                     f"{float(r['MinNs'])/1e3:.2f} | {float(r['MaxNs'])/1e3:.2f} | {float(r['Percentage']):.2f}% |")
+    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def summarize_lds(lds_dir, cmd):
@@ -437,6 +453,9 @@ def run_served(args):
 
 def main():
     args = parse()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats, args.summary_cmd)
+        return
     if args.summarize:
         summarize(*args.summarize, args.summary_cmd)
         if args.lds_dir:
