@@ -313,3 +313,17 @@ def test_dense_without_links(torch_dev):
                     got, c = gpu_occ(x, yd, (q, alpha, w), (64, B.HC_SCHED_DENSE, 0, 0))
                     want = O.occurrences(x, y)
                     assert c == want.size and np.array_equal(got, want), (sigma, m, q, alpha, w)
+
+
+def test_markov_full_size_sampled(torch_dev):
+    """The 256 MiB order-2 Markov text (the skewed-text workload), library
+    defaults, two sampled patterns per length, complete lists compared."""
+    y = W.markov_text(256 << 20)
+    yd = to_dev(y, torch_dev)
+    for m in W.MARKOV_LENGTHS:
+        for off, x in W.markov_patterns(y, m, count=2):
+            announce("markov full", m, off)
+            want = O.occurrences(x, y)
+            got, c = gpu_occ(x, yd, None, None, cap=int(want.size) + 16)
+            assert c == want.size and np.array_equal(got, want), (m, off)
+    del yd
