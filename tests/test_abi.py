@@ -120,6 +120,17 @@ def test_null_arguments_are_rejected():
     big = (ctypes.c_int64 * 1)(4097)
     assert L.hc_autotune(ctypes.c_void_p(16), 1 << 20, big, 1, 3, None, None) == B.HC_EINVAL
     assert L.hc_serve_next_done(None, None, 0) == B.HC_EINVAL
+    assert L.hc_serve_create(None, None, 0, 1 << 20, None, ctypes.byref(out)) == B.HC_EINVAL
+    assert L.hc_serve_submit(None, 0, b"abc", 3, None) == B.HC_EINVAL
+    assert L.hc_serve_stats(None, None, None, None, None) == B.HC_EINVAL
+    assert L.hc_serve_destroy(None) == B.HC_EINVAL
+    assert L.hc_batch_plan_create(None, None, ctypes.byref(out)) == B.HC_EINVAL
+    total = ctypes.c_int64()
+    assert L.hc_search_batched(None, None, None, 0, None, ctypes.byref(total), None) == B.HC_EINVAL
+    assert L.hc_batch_plan_run(None, None, 0, None, ctypes.byref(total), None) == B.HC_EINVAL
+    L.hc_batch_plan_free(None)
+    assert L.hc_preprocess_many(None, None, 1, None, None, 4096, None, None, None) == B.HC_EINVAL
+    assert L.hc_preprocess_many(None, None, 0, None, None, 4096, None, None, None) == B.HC_OK
     L.hc_autotune_reset()
 
 
