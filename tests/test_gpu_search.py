@@ -327,3 +327,32 @@ def test_markov_full_size_sampled(torch_dev):
             got, c = gpu_occ(x, yd, None, None, cap=int(want.size) + 16)
             assert c == want.size and np.array_equal(got, want), (m, off)
     del yd
+
+
+def test_repeated_runs_identical(torch_dev):
+    """The same searches repeated give byte-identical output (catches races in
+    marking, parked chain walks and compaction): a periodic text where long
+    patterns occur often and most windows need long chain walks."""
+    import torch
+
+    g = np.random.default_rng(21)
+    block = g.integers(0, 4, size=5003, dtype=np.uint8) + ord("a")
+    y = np.tile(block, 400)
+    yd = to_dev(y, torch_dev)
+    for m, q, sched in ((1000, 8, 1), (1000, 3, 1), (64, 4, 1), (4, 2, 3), (300, 5, 2)):
+        x = y[777:777 + m].tobytes()
+        want = O.occurrences(x, y)
+        p = B.hc_preprocess(x, (q, 12, 32))
+        out = torch.empty(want.size + 16, dtype=torch.int64, device=torch_dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=torch_dev)
+        first = None
+        for rep in range(12):
+            announce("repeat identical", m, q, sched, rep)
+            B.hc_search_async(p, yd, out, cnt, launch=(0, sched, 0, 0))
+            torch.cuda.synchronize()
+            got = out[:int(cnt.item())].cpu().numpy().copy()
+            if first is None:
+                first = got
+                assert np.array_equal(got, want), (m, q)
+            else:
+                assert np.array_equal(got, first), (m, q, rep)

@@ -213,3 +213,21 @@ def test_completion_queue_reports_each_request_once(texts):
     finally:
         srv.close()
     check(host, reqs, got)
+
+
+def test_destroy_with_work_in_flight(texts):
+    """Destroying a server while requests are queued and running neither
+    hangs nor faults; a new server afterwards serves correctly."""
+    host, dev = texts
+    srv = B.Server(dev, 4 * (8192 + 4128 + 4096 * 8))   # four slots: most requests wait
+    reqs = requests(host, 200, 6)
+    announce("serve destroy in flight")
+    for t, x in reqs:
+        srv.submit(t, x)
+    srv.close()
+    srv = B.Server(dev, 64 * MiB)
+    try:
+        got = [srv.result(srv.submit(t, x)) for t, x in reqs[:20]]
+    finally:
+        srv.close()
+    check(host, reqs[:20], got)
