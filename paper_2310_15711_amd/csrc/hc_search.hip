@@ -410,17 +410,20 @@ struct EmitArgs {
 __device__ __forceinline__ uint32_t sum_counts(const uint32_t *counts, uint32_t r, uint32_t *lds_w) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nvec = r / 4u;
-    const uint4 *c4 = reinterpret_cast<const uint4 *>(counts);
+    // 12 vectors per thread in flight at once: one round trip covers the
+    // 12,288 counts of a 256 MiB text at the default tile size
+    constexpr int kVec = 12;
+    global_u32x4 *c4 = (global_u32x4 *)counts;
     uint32_t part = 0;
-    for (uint32_t base = 0; base < nvec; base += 4u * kBlock) {
-        uint4 v[4];
+    for (uint32_t base = 0; base < nvec; base += kVec * kBlock) {
+        u32x4 v[kVec];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kVec; ++k) {
             const uint32_t i = base + k * kBlock + tid;
-            v[k] = i < nvec ? c4[i] : make_uint4(0, 0, 0, 0);
+            v[k] = i < nvec ? c4[i] : u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) part += v[k].x + v[k].y + v[k].z + v[k].w;
+        for (int k = 0; k < kVec; ++k) part += v[k].x + v[k].y + v[k].z + v[k].w;
     }
     if (tid < (r & 3u)) part += counts[nvec * 4u + tid];
     uint32_t total;
