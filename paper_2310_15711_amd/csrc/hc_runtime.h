@@ -25,10 +25,14 @@ const DeviceInfo &device_info();
 // per-tile results of the search phase (counts, short position slots, spilled
 // bitmaps). Calls on one stream serialise, so one workspace per stream is never
 // used by two launches at once.
+// Occurrences a tile keeps as a list of tile-relative starts; denser tiles
+// keep their bitmap.
+constexpr uint32_t kSlot = 128;
+
 struct Workspace {
     void *ctl = nullptr;          // control words (work tickets), zero-initialised
     uint32_t *counts = nullptr;   // tiles_cap entries
-    uint32_t *slots = nullptr;    // tiles_cap * 32 entries
+    uint32_t *slots = nullptr;    // tiles_cap * kSlot entries
     uint32_t *spill = nullptr;    // spill_words_cap entries
     uint32_t tiles_cap = 0;
     uint64_t spill_words_cap = 0;

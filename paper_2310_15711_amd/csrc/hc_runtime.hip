@@ -60,7 +60,7 @@ hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Works
             ws->tiles_cap = 0;
             const uint32_t cap = std::max<uint32_t>(tiles, 4096);
             if (hipMalloc(reinterpret_cast<void **>(&ws->counts), sizeof(uint32_t) * cap) != hipSuccess ||
-                hipMalloc(reinterpret_cast<void **>(&ws->slots), sizeof(uint32_t) * 32u * cap) != hipSuccess)
+                hipMalloc(reinterpret_cast<void **>(&ws->slots), sizeof(uint32_t) * kSlot * cap) != hipSuccess)
                 return HC_ENOMEM;
             ws->tiles_cap = cap;
         }

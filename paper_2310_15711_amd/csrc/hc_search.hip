@@ -24,9 +24,6 @@
 
 namespace hc {
 
-// Positions a tile keeps in its slot; denser tiles store their bitmap.
-constexpr uint32_t kSlot = 32;
-
 // Internal schedule code of the SHC (sentinel) variant.
 constexpr int kSchedShc = 16;
 
@@ -394,7 +391,8 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
 // Ordered output: workgroup b writes the occurrences of tiles
 // [b * per, (b + 1) * per) in tile order. Its offset is the sum of the counts
 // of all earlier tiles, read in parallel; the search kernel has finished, so
-// every count, slot and spilled bitmap is visible.
+// every count, slot and spilled bitmap is visible. Within the workgroup each
+// wavefront takes every fourth tile, so four tiles are in progress at once.
 struct EmitArgs {
     uint32_t n_tiles, tile, per;
     uint64_t starts;
@@ -432,11 +430,36 @@ __device__ __forceinline__ uint32_t sum_counts(const uint32_t *counts, uint32_t 
     return total;
 }
 
+// Bitmap words of a spilled tile read by one wavefront per batch: one word
+// per lane per round, all rounds' loads in flight together.
+constexpr int kEmitRounds = 16;
+
+// Tiles with at most kStageTile occurrences and at most kWave * kLaneWords
+// bitmap words are ordered in one pass.
+constexpr uint32_t kStageTile = 1024;
+constexpr int kLaneWords = 32;
+
+// Workgroups of the ordered output per compute unit.
+constexpr uint32_t kEmitPerCu = 4;
+
+// Orders LDS accesses of one wavefront (its lanes execute in lock step and
+// its LDS operations complete in issue order; this only stops the compiler
+// from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
     __shared__ uint32_t lds_w[4];
     __shared__ uint32_t cnt[kBlock];
     __shared__ uint32_t off[kBlock];
-    const uint32_t tid = threadIdx.x;
+    // per wavefront, positions in ascending order before they are stored:
+    // a whole tile's (tile-relative, 32 bits), or one round's of 64 bitmap
+    // words (relative to the round's first window, 16 bits)
+    __shared__ uint32_t stage[kBlock / kWave][kStageTile];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const uint32_t tile_words = A.tile / 32u;
     if (A.n_tiles == 0) {
         if (blockIdx.x == 0 && tid == 0) *A.d_count = 0;
@@ -455,33 +478,73 @@ __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
     const bool last = r1 == A.n_tiles;
     if (range_total == 0u && !last) return;   // nothing to write, and no total to report
     const int64_t prefix = sum_counts(A.counts, r0, lds_w);
-    for (uint32_t j = 0; j < nc; ++j) {
+    uint32_t *st32 = stage[wv];
+    uint16_t *st = reinterpret_cast<uint16_t *>(st32);
+    for (uint32_t j = wv; j < nc; j += kBlock / kWave) {
         const uint32_t c = cnt[j];
         if (c == 0u) continue;
         const uint32_t t = r0 + j;
         const uint64_t tile_lo = uint64_t(t) * A.tile;
-        const int64_t base = prefix + off[j];
+        int64_t base = prefix + off[j];
         if (c <= kSlot) {
-            if (tid < c && base + tid < A.cap)
-                A.out[base + tid] = int64_t(tile_lo + A.slots[uint64_t(t) * kSlot + tid]);
-        } else {
-            const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
-            const uint32_t words = (S + 31u) / 32u;
-            const uint32_t wpt = (words + kBlock - 1u) / kBlock;
-            const uint32_t w0 = min(words, tid * wpt), w1 = min(words, w0 + wpt);
-            const uint32_t *sb = A.spill + uint64_t(t) * tile_words;
-            uint32_t k = 0;
-            for (uint32_t i = w0; i < w1; ++i) k += __popc(sb[i]);
-            uint32_t tot;
-            int64_t idx = base + block_exclusive_scan(k, lds_w, &tot);
-            lds_barrier();
-            for (uint32_t i = w0; i < w1 && idx < A.cap; ++i) {
-                uint32_t b = sb[i];
-                while (b && idx < A.cap) {
-                    const uint32_t bit = __builtin_ctz(b);
+            for (uint32_t o = lane; o < c; o += kWave)
+                if (base + o < A.cap) A.out[base + o] = int64_t(tile_lo + A.slots[uint64_t(t) * kSlot + o]);
+            continue;
+        }
+        const uint32_t S = uint32_t(min<uint64_t>(A.tile, A.starts - tile_lo));
+        const uint32_t words = (S + 31u) / 32u;   // words past these may be stale
+        const uint32_t *sb = A.spill + uint64_t(t) * tile_words;
+        if (c <= kStageTile && words <= kWave * kLaneWords) {
+            // one pass: lane l owns the R consecutive words from l * R, so one
+            // scan orders the whole tile
+            const uint32_t R = (words + kWave - 1u) / kWave, w0 = lane * R;
+            uint32_t v[kLaneWords], pc = 0;
+#pragma unroll
+            for (int k = 0; k < kLaneWords; ++k) {
+                const uint32_t i = w0 + uint32_t(k);
+                v[k] = uint32_t(k) < R && i < words ? sb[i] : 0u;
+                pc += __popc(v[k]);
+            }
+            uint32_t e = wave_inclusive_sum(pc) - pc;
+#pragma unroll
+            for (int k = 0; k < kLaneWords; ++k) {
+                uint32_t b = v[k];
+                while (b) {
+                    if (e < kStageTile) st32[e] = (w0 + uint32_t(k)) * 32u + uint32_t(__builtin_ctz(b));
+                    ++e;
                     b &= b - 1u;
-                    A.out[idx++] = int64_t(tile_lo + i * 32u + bit);
                 }
+            }
+            wave_lds_sync();
+            for (uint32_t o = lane; o < c; o += kWave)
+                if (base + o < A.cap) A.out[base + o] = int64_t(tile_lo + st32[o]);
+            wave_lds_sync();   // read before the next tile writes
+            continue;
+        }
+        for (uint32_t w0 = 0; w0 < words && base < A.cap; w0 += kEmitRounds * kWave) {
+            uint32_t v[kEmitRounds];
+#pragma unroll
+            for (int k = 0; k < kEmitRounds; ++k) {
+                const uint32_t i = w0 + uint32_t(k) * kWave + lane;
+                v[k] = i < words ? sb[i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kEmitRounds; ++k) {
+                const uint32_t pc = __popc(v[k]);
+                const uint32_t incl = wave_inclusive_sum(pc);
+                const uint32_t tot = __builtin_amdgcn_readlane(incl, kWave - 1);
+                if (tot == 0u) continue;
+                uint32_t e = incl - pc, b = v[k];
+                while (b) {
+                    st[e++] = uint16_t(lane * 32u + uint32_t(__builtin_ctz(b)));
+                    b &= b - 1u;
+                }
+                wave_lds_sync();
+                const uint64_t lo = tile_lo + uint64_t(w0 + uint32_t(k) * kWave) * 32u;
+                for (uint32_t o = lane; o < tot; o += kWave)
+                    if (base + o < A.cap) A.out[base + o] = int64_t(lo + st[o]);
+                wave_lds_sync();   // read before the next round writes
+                base += tot;
             }
         }
     }
@@ -713,7 +776,7 @@ static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, c
     // at most 256 tiles per workgroup of the ordered output
     const uint32_t emit_grid = std::max<uint32_t>(
         std::max<uint32_t>(1, (n_tiles + kBlock - 1) / kBlock),
-        std::min<uint32_t>(std::max<uint32_t>(n_tiles, 1), uint32_t(di.cus) * 2u));
+        std::min<uint32_t>(std::max<uint32_t>(n_tiles, 1), uint32_t(di.cus) * kEmitPerCu));
     E.per = (n_tiles + emit_grid - 1) / emit_grid;
     E.starts = starts;
     E.counts = ws->counts;

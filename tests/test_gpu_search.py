@@ -144,6 +144,33 @@ def test_overflow_reports_total_and_prefix(torch_dev):
     assert st == B.HC_EOVERFLOW and c == n - 1
 
 
+def test_dense_output_every_tile_size(torch_dev):
+    """Tiles whose occurrences are kept as bitmaps, at every tile size the
+    launches use (one to many batches of bitmap words per tile), full and
+    periodic densities, and capacities that end inside a tile."""
+    n = 300_007
+    cases = [(np.full(n, 7, dtype=np.uint8), bytes([7, 7]), 1),
+             (np.frombuffer(b"abc" * (n // 3), dtype=np.uint8), b"ab", 3),
+             (np.frombuffer(b"aaaab" * (n // 5), dtype=np.uint8), b"aa", None)]
+    # a few to a few hundred occurrences per tile
+    g = np.random.default_rng(17)
+    for sigma, m in ((4, 4), (2, 6), (20, 2)):
+        y = g.integers(0, sigma, size=n, dtype=np.uint8) + 65
+        cases.append((y, y[1000:1000 + m].tobytes(), None))
+    for y, x, period in cases:
+        yd = to_dev(y, torch_dev)
+        want = O.occurrences(x, y)
+        if period:
+            assert np.array_equal(want, np.arange(0, y.size - len(x) + 1, period))
+        for launch in [(36, 0, 0, 0), (64, B.HC_SCHED_DENSE, 0, 0), (100, 0, 0, 0), (132, 0, 0, 0),
+                       (200, 0, 0, 0), (512, 0, B.HC_VARIANT_SPARSE, 0), (4096, 0, B.HC_VARIANT_SPARSE, 0)]:
+            for cap in (want.size, 40_017):
+                announce("dense output", x, launch, cap)
+                got, c = gpu_occ(x, yd, (2, 10, 16), launch, cap=cap)
+                assert c == want.size
+                assert np.array_equal(got, want[:cap]), (x, launch, cap)
+
+
 def test_edges(torch_dev):
     import torch
 
