@@ -653,11 +653,14 @@ __device__ __forceinline__ TileResult shc_tile(const uint32_t *__restrict__ t32,
 // which is linked or marked). With m <= 4 the whole window is in the word
 // already loaded, so it is compared with x right there and the verification
 // pass only counts.
-template <int Q, typename WT, int C>
-__device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t32, uint32_t tb,
-                                                 const WT *__restrict__ F, const uint32_t *__restrict__ x32,
-                                                 const PatternView &P, uint32_t S, uint32_t *bm, uint32_t *misc,
-                                                 uint32_t &it) {
+// Marks the tile's windows that pass the test; returns whether any did.
+// The bitmap is all zero on entry (every tile leaves it cleared), so only
+// nonzero bytes are written. WIDE: alpha = 16 (the 16-bit lanes of the
+// packed hashes have no spare top bit).
+template <int Q, typename WT, int C, bool WIDE>
+__device__ __forceinline__ bool dense_mark(const uint32_t *__restrict__ t32, uint32_t tb, const WT *__restrict__ F,
+                                           const uint32_t *__restrict__ x32, const PatternView &P, uint32_t S,
+                                           uint32_t *bm) {
     static_assert(Q >= 1 && Q <= 4, "dense schedule hashes 4-byte words");
     constexpr int E = 8 + C * Q;                  // q-gram ends per group of 8 windows
     constexpr int NW = ((E - 1) >> 2) + 2;        // aligned words covering them
@@ -668,6 +671,7 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
     // x's m bytes as the top m bytes of a word ending at the window end
     const uint32_t xw = inline_check ? (x32[0] << (8u * (4u - P.m))) : 0u;
     const uint32_t xmask = inline_check ? (0xFFFFFFFFu << (8u * (4u - P.m))) : 0u;
+    const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
     bool found = false;
     for (uint32_t g = threadIdx.x; g < groups; g += kThreads) {
         const uint32_t st0 = 8u * g;
@@ -685,63 +689,68 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
         if constexpr (C == 0) {
             // the 8 window-end hashes two at a time in 16-bit lanes: column
             // k holds byte k of every window's q-gram (8 consecutive text
-            // bytes), zero-extended in pairs; shifts and sums wrap mod 2^16,
-            // which 2^alpha divides (alpha <= 16)
+            // bytes), zero-extended in pairs, and is added times 2^(s k);
+            // sums wrap mod 2^16, which 2^alpha divides (alpha <= 16)
             typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
             u16x2 acc[4];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 constexpr int o0 = 4 - Q;   // offset of column 0 from p0
-                const int o = o0 + k;
-                const uint32_t lo = o ? __builtin_amdgcn_alignbyte(w[1], w[0], o) : w[0];
-                const uint32_t hi = o ? __builtin_amdgcn_alignbyte(w[2], w[1], o) : w[1];
-                const uint32_t pr[4] = {__builtin_amdgcn_perm(0u, lo, 0x0C010C00u),
-                                        __builtin_amdgcn_perm(0u, lo, 0x0C030C02u),
-                                        __builtin_amdgcn_perm(0u, hi, 0x0C010C00u),
-                                        __builtin_amdgcn_perm(0u, hi, 0x0C030C02u)};
-                const uint16_t sk = uint16_t(P.s * uint32_t(k));
+                const uint32_t o = uint32_t(o0 + k);
+                // bytes o + 2i and o + 2i + 1 of w[0..2], zero-extended into
+                // the two halves (v_perm numbers the bytes of {src0, src1}
+                // from src1's lowest; 0x0C yields a zero byte)
+                const uint32_t pr[4] = {
+                    __builtin_amdgcn_perm(w[1], w[0], 0x0C000C00u | o | ((o + 1u) << 16)),
+                    __builtin_amdgcn_perm(w[1], w[0], 0x0C000C00u | (o + 2u) | ((o + 3u) << 16)),
+                    __builtin_amdgcn_perm(w[2], w[1], 0x0C000C00u | o | ((o + 1u) << 16)),
+                    __builtin_amdgcn_perm(w[2], w[1], 0x0C000C00u | (o + 2u) | ((o + 3u) << 16))};
+                // s k <= alpha - s < 16
+                const uint16_t mk = uint16_t(1u << (P.s * uint32_t(k)));
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const u16x2 r = __builtin_bit_cast(u16x2, pr[i]);
-                    acc[i] = k == 0 ? r : acc[i] + (r << u16x2{sk, sk});
+                    acc[i] = k == 0 ? r : acc[i] + r * u16x2{mk, mk};
                 }
             }
-            const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
-            uint32_t any = 0, dd[4];
+            // per 16-bit half t = (H ^ H_v) mod 2^alpha; bit 15 of nz is set
+            // iff t != 0 (alpha <= 15: t + 0x7FFF cannot carry out of the half)
+            uint32_t nz[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                dd[i] = (__builtin_bit_cast(uint32_t, acc[i]) & mask2) ^ hv2;   // zero half: H = H_v
-                any |= (dd[i] - 0x00010001u) & ~dd[i] & 0x80008000u;
+                const uint32_t t = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
+                nz[i] = WIDE ? (((t & 0x7FFF7FFFu) + 0x7FFF7FFFu) | t) : (t + 0x7FFF7FFFu);
             }
-            if (any) {
+            if ((nz[0] & nz[1] & nz[2] & nz[3] & 0x80008000u) != 0x80008000u) {
+                // window 2i is the low half of pair i, window 2i + 1 the high
+                uint32_t e = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    bits |= (uint32_t((dd[i] & 0xFFFFu) == 0u) | (uint32_t((dd[i] >> 16) == 0u) << 1)) << (2 * i);
+                for (int i = 0; i < 4; ++i) e |= (~nz[i] & 0x80008000u) >> (15 - 2 * i);
+                bits = (e | (e >> 15)) & 0xFFu;
                 if (inline_check) {   // the window is in the word that ends it
                     uint32_t eq = 0;
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
                         const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
                                                       : w[j >> 2];
-                        eq |= uint32_t((word & xmask) == xw) << j;
+                        eq |= uint32_t(((word ^ xw) & xmask) == 0u) << j;
                     }
                     bits &= eq;
                 }
             }
-        }
-        uint32_t h[E], wend[8];
+        } else {
+            uint32_t h[E], wend[8];
 #pragma unroll
-        for (int j = 0; j < E && C > 0; ++j) {
-            // bytes a0 + j - 3 .. a0 + j
-            const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
-                                          : w[j >> 2];
-            if (j >= C * Q) wend[j - C * Q] = word;
-            uint32_t v = 0;
+            for (int j = 0; j < E; ++j) {
+                // bytes a0 + j - 3 .. a0 + j
+                const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
+                                              : w[j >> 2];
+                if (j >= C * Q) wend[j - C * Q] = word;
+                uint32_t v = 0;
 #pragma unroll
-            for (int k = Q - 1; k >= 0; --k) v = (v << P.s) + __builtin_amdgcn_ubfe(word, 8 * (4 - Q + k), 8);
-            h[j] = v & P.mask;
-        }
-        if constexpr (C > 0) {
+                for (int k = Q - 1; k >= 0; --k) v = (v << P.s) + __builtin_amdgcn_ubfe(word, 8 * (4 - Q + k), 8);
+                h[j] = v & P.mask;
+            }
             WT z[E - Z0];
 #pragma unroll
             for (int j = Z0; j < E; ++j) z[j - Z0] = F[h[j]];
@@ -754,20 +763,35 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
                 alive = alive && h[e - C * Q] == P.hv;
                 bits |= uint32_t(alive) << j;
             }
-        }
-        if (C > 0 && inline_check) {
-            uint32_t eq = 0;
+            if (inline_check) {
+                uint32_t eq = 0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) eq |= uint32_t((wend[j] & xmask) == xw) << j;
-            bits &= eq;
+                for (int j = 0; j < 8; ++j) eq |= uint32_t(((wend[j] ^ xw) & xmask) == 0u) << j;
+                bits &= eq;
+            }
         }
-        if (st0 + 8u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
-        bm8[g] = uint8_t(bits);
-        found |= bits != 0u;
+        if (bits) {
+            if (st0 + 8u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
+            bm8[g] = uint8_t(bits);
+            found |= bits != 0u;
+        }
     }
+    return found;
+}
+
+template <int Q, typename WT, int C>
+__device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                 const WT *__restrict__ F, const uint32_t *__restrict__ x32,
+                                                 const PatternView &P, uint32_t S, uint32_t *bm, uint32_t *misc,
+                                                 uint32_t &it) {
+    bool found;
+    if (C == 0 && P.mask > 0x7FFFu)
+        found = dense_mark<Q, WT, C, true>(t32, tb, F, x32, P, S, bm);
+    else
+        found = dense_mark<Q, WT, C, false>(t32, tb, F, x32, P, S, bm);
     if (found) misc[8 + (it & 1u)] = 1u;
     lds_barrier();
-    return verify_tile(t32, tb, x32, P, S, bm, misc, it, inline_check);
+    return verify_tile(t32, tb, x32, P, S, bm, misc, it, P.m <= 4u);
 }
 
 }  // namespace hc
