@@ -655,24 +655,101 @@ __device__ __forceinline__ TileResult shc_tile(const uint32_t *__restrict__ t32,
 // pass only counts.
 // Marks the tile's windows that pass the test; returns whether any did.
 // The bitmap is all zero on entry (every tile leaves it cleared), so only
-// nonzero bytes are written. WIDE: alpha = 16 (the 16-bit lanes of the
-// packed hashes have no spare top bit).
-template <int Q, typename WT, int C, bool WIDE>
-__device__ __forceinline__ bool dense_mark(const uint32_t *__restrict__ t32, uint32_t tb, const WT *__restrict__ F,
-                                           const uint32_t *__restrict__ x32, const PatternView &P, uint32_t S,
-                                           uint32_t *bm) {
+// nonzero bytes are written.
+//
+// No links (m < 2q): 16 windows per lane and step. The 16 window-end hashes
+// are formed two at a time in 16-bit lanes: column k holds byte k of every
+// window's q-gram, zero-extended in pairs, and is added times 2^(s k); sums
+// wrap mod 2^16, which 2^alpha divides (alpha <= 16). WIDE: alpha = 16 (no
+// spare top bit in a lane for the add-based zero test).
+template <int Q, bool WIDE>
+__device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t32, uint32_t tb,
+                                                  const uint32_t *__restrict__ x32, const PatternView &P,
+                                                  uint32_t S, uint32_t *bm) {
     static_assert(Q >= 1 && Q <= 4, "dense schedule hashes 4-byte words");
-    constexpr int E = 8 + C * Q;                  // q-gram ends per group of 8 windows
-    constexpr int NW = ((E - 1) >> 2) + 2;        // aligned words covering them
-    constexpr int Z0 = C > 0 ? Q : 0;             // first q-gram end whose word is needed
-    uint8_t *bm8 = reinterpret_cast<uint8_t *>(bm);
-    const uint32_t groups = (S + 7u) / 8u;
+    typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+    uint16_t *bm16 = reinterpret_cast<uint16_t *>(bm);
+    const uint32_t steps = (S + 15u) / 16u;
     const bool inline_check = P.m <= 4u;
     // x's m bytes as the top m bytes of a word ending at the window end
     const uint32_t xw = inline_check ? (x32[0] << (8u * (4u - P.m))) : 0u;
     const uint32_t xmask = inline_check ? (0xFFFFFFFFu << (8u * (4u - P.m))) : 0u;
     const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
-    bool found = false;
+    uint32_t any = 0;
+    for (uint32_t g = threadIdx.x; g < steps; g += kThreads) {
+        const uint32_t st0 = 16u * g;
+        // window st0 + j ends at LDS byte a0 + j; w[i] = bytes p0 + 4i .. p0 + 4i + 3
+        const uint32_t a0 = tb + st0 + P.m - 1u;
+        const uint32_t p0 = a0 - 3u, base = p0 >> 2, sh = p0 & 3u;
+        uint32_t d[6], w[5];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) d[i] = t32[base + i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+        // pair i = windows 2i (low half) and 2i + 1 (high half); byte k of
+        // their q-grams sits at p0 + (4 - Q) + k + 2i
+        u16x2 acc[8];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const uint32_t mk = 1u << (P.s * uint32_t(k));   // s k <= alpha - s < 16
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                // v_perm numbers the bytes of {src0, src1} from src1's lowest;
+                // selector 0x0C yields a zero byte
+                const uint32_t o = uint32_t(4 - Q + k + 2 * (i & 1));
+                const uint32_t pr = __builtin_amdgcn_perm(w[(i >> 1) + 1], w[i >> 1],
+                                                          0x0C000C00u | o | ((o + 1u) << 16));
+                const u16x2 r = __builtin_bit_cast(u16x2, pr);
+                acc[i] = k == 0 ? r : acc[i] + r * u16x2{uint16_t(mk), uint16_t(mk)};
+            }
+        }
+        // per half t = (H ^ H_v) mod 2^alpha; bit 15 of nz is set iff t != 0
+        // (alpha <= 15: t + 0x7FFF cannot carry out of the half)
+        uint32_t nz[8], all = 0x80008000u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t t = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
+            nz[i] = WIDE ? (((t & 0x7FFF7FFFu) + 0x7FFF7FFFu) | t) : (t + 0x7FFF7FFFu);
+            all &= nz[i];
+        }
+        if (all == 0x80008000u) continue;   // no window-end hash equals H_v
+        uint32_t e = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e |= (~nz[i] & 0x80008000u) >> (15 - 2 * i);
+        uint32_t bits = (e | (e >> 15)) & 0xFFFFu;
+        if (inline_check) {   // the window is in the word that ends it
+            uint32_t eq = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
+                                              : w[j >> 2];
+                eq |= uint32_t(((word ^ xw) & xmask) == 0u) << j;
+            }
+            bits &= eq;
+        }
+        if (st0 + 16u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
+        if (bits) bm16[g] = uint16_t(bits);
+        any |= bits;
+    }
+    return any != 0u;
+}
+
+// With links (C = m / q - 1 >= 1): 8 windows per lane and step; the 8
+// window-end q-grams and the C * q q-gram ends behind them are hashed one by
+// one and their words looked up.
+template <int Q, typename WT, int C>
+__device__ __forceinline__ bool dense_mark(const uint32_t *__restrict__ t32, uint32_t tb, const WT *__restrict__ F,
+                                           const uint32_t *__restrict__ x32, const PatternView &P, uint32_t S,
+                                           uint32_t *bm) {
+    static_assert(Q >= 1 && Q <= 4 && C >= 1, "dense schedule hashes 4-byte words");
+    constexpr int E = 8 + C * Q;                  // q-gram ends per group of 8 windows
+    constexpr int NW = ((E - 1) >> 2) + 2;        // aligned words covering them
+    uint8_t *bm8 = reinterpret_cast<uint8_t *>(bm);
+    const uint32_t groups = (S + 7u) / 8u;
+    const bool inline_check = P.m <= 4u;
+    const uint32_t xw = inline_check ? (x32[0] << (8u * (4u - P.m))) : 0u;
+    const uint32_t xmask = inline_check ? (0xFFFFFFFFu << (8u * (4u - P.m))) : 0u;
+    uint32_t any = 0;
     for (uint32_t g = threadIdx.x; g < groups; g += kThreads) {
         const uint32_t st0 = 8u * g;
         // LDS position of the earliest q-gram end needed, and the first byte
@@ -685,98 +762,42 @@ __device__ __forceinline__ bool dense_mark(const uint32_t *__restrict__ t32, uin
         uint32_t w[NW];
 #pragma unroll
         for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+        uint32_t h[E], wend[8];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            // bytes a0 + j - 3 .. a0 + j
+            const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
+                                          : w[j >> 2];
+            if (j >= C * Q) wend[j - C * Q] = word;
+            uint32_t v = 0;
+#pragma unroll
+            for (int k = Q - 1; k >= 0; --k) v = (v << P.s) + __builtin_amdgcn_ubfe(word, 8 * (4 - Q + k), 8);
+            h[j] = v & P.mask;
+        }
+        WT z[E - Q];
+#pragma unroll
+        for (int j = Q; j < E; ++j) z[j - Q] = F[h[j]];
         uint32_t bits = 0;
-        if constexpr (C == 0) {
-            // the 8 window-end hashes two at a time in 16-bit lanes: column
-            // k holds byte k of every window's q-gram (8 consecutive text
-            // bytes), zero-extended in pairs, and is added times 2^(s k);
-            // sums wrap mod 2^16, which 2^alpha divides (alpha <= 16)
-            typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
-            u16x2 acc[4];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                constexpr int o0 = 4 - Q;   // offset of column 0 from p0
-                const uint32_t o = uint32_t(o0 + k);
-                // bytes o + 2i and o + 2i + 1 of w[0..2], zero-extended into
-                // the two halves (v_perm numbers the bytes of {src0, src1}
-                // from src1's lowest; 0x0C yields a zero byte)
-                const uint32_t pr[4] = {
-                    __builtin_amdgcn_perm(w[1], w[0], 0x0C000C00u | o | ((o + 1u) << 16)),
-                    __builtin_amdgcn_perm(w[1], w[0], 0x0C000C00u | (o + 2u) | ((o + 3u) << 16)),
-                    __builtin_amdgcn_perm(w[2], w[1], 0x0C000C00u | o | ((o + 1u) << 16)),
-                    __builtin_amdgcn_perm(w[2], w[1], 0x0C000C00u | (o + 2u) | ((o + 3u) << 16))};
-                // s k <= alpha - s < 16
-                const uint16_t mk = uint16_t(1u << (P.s * uint32_t(k)));
+        for (int j = 0; j < 8; ++j) {
+            const int e = j + C * Q;          // index of the window-end q-gram
+            bool alive = z[e - Q] != 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const u16x2 r = __builtin_bit_cast(u16x2, pr[i]);
-                    acc[i] = k == 0 ? r : acc[i] + r * u16x2{mk, mk};
-                }
-            }
-            // per 16-bit half t = (H ^ H_v) mod 2^alpha; bit 15 of nz is set
-            // iff t != 0 (alpha <= 15: t + 0x7FFF cannot carry out of the half)
-            uint32_t nz[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t t = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
-                nz[i] = WIDE ? (((t & 0x7FFF7FFFu) + 0x7FFF7FFFu) | t) : (t + 0x7FFF7FFFu);
-            }
-            if ((nz[0] & nz[1] & nz[2] & nz[3] & 0x80008000u) != 0x80008000u) {
-                // window 2i is the low half of pair i, window 2i + 1 the high
-                uint32_t e = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) e |= (~nz[i] & 0x80008000u) >> (15 - 2 * i);
-                bits = (e | (e >> 15)) & 0xFFu;
-                if (inline_check) {   // the window is in the word that ends it
-                    uint32_t eq = 0;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
-                                                      : w[j >> 2];
-                        eq |= uint32_t(((word ^ xw) & xmask) == 0u) << j;
-                    }
-                    bits &= eq;
-                }
-            }
-        } else {
-            uint32_t h[E], wend[8];
-#pragma unroll
-            for (int j = 0; j < E; ++j) {
-                // bytes a0 + j - 3 .. a0 + j
-                const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
-                                              : w[j >> 2];
-                if (j >= C * Q) wend[j - C * Q] = word;
-                uint32_t v = 0;
-#pragma unroll
-                for (int k = Q - 1; k >= 0; --k) v = (v << P.s) + __builtin_amdgcn_ubfe(word, 8 * (4 - Q + k), 8);
-                h[j] = v & P.mask;
-            }
-            WT z[E - Z0];
-#pragma unroll
-            for (int j = Z0; j < E; ++j) z[j - Z0] = F[h[j]];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int e = j + C * Q;          // index of the window-end q-gram
-                bool alive = z[e - Z0] != 0;
-#pragma unroll
-                for (int k = 1; k <= C; ++k) alive = alive && linked(z[e - (k - 1) * Q - Z0], h[e - k * Q]);
-                alive = alive && h[e - C * Q] == P.hv;
-                bits |= uint32_t(alive) << j;
-            }
-            if (inline_check) {
-                uint32_t eq = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) eq |= uint32_t(((wend[j] ^ xw) & xmask) == 0u) << j;
-                bits &= eq;
-            }
+            for (int k = 1; k <= C; ++k) alive = alive && linked(z[e - (k - 1) * Q - Q], h[e - k * Q]);
+            alive = alive && h[e - C * Q] == P.hv;
+            bits |= uint32_t(alive) << j;
         }
-        if (bits) {
-            if (st0 + 8u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
-            bm8[g] = uint8_t(bits);
-            found |= bits != 0u;
+        if (inline_check) {
+            uint32_t eq = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) eq |= uint32_t(((wend[j] ^ xw) & xmask) == 0u) << j;
+            bits &= eq;
         }
+        if (st0 + 8u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
+        if (bits) bm8[g] = uint8_t(bits);
+        any |= bits;
     }
-    return found;
+    return any != 0u;
 }
 
 template <int Q, typename WT, int C>
@@ -785,10 +806,11 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
                                                  const PatternView &P, uint32_t S, uint32_t *bm, uint32_t *misc,
                                                  uint32_t &it) {
     bool found;
-    if (C == 0 && P.mask > 0x7FFFu)
-        found = dense_mark<Q, WT, C, true>(t32, tb, F, x32, P, S, bm);
+    if constexpr (C == 0)
+        found = P.mask > 0x7FFFu ? dense_mark_nolink<Q, true>(t32, tb, x32, P, S, bm)
+                                 : dense_mark_nolink<Q, false>(t32, tb, x32, P, S, bm);
     else
-        found = dense_mark<Q, WT, C, false>(t32, tb, F, x32, P, S, bm);
+        found = dense_mark<Q, WT, C>(t32, tb, F, x32, P, S, bm);
     if (found) misc[8 + (it & 1u)] = 1u;
     lds_barrier();
     return verify_tile(t32, tb, x32, P, S, bm, misc, it, P.m <= 4u);
