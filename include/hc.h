@@ -87,7 +87,10 @@ enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENS
 enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIANT_SPARSE = 3 };
 
 /* Launch shape of the search kernel. A field set to 0 is chosen by the
- * library (the autotuner's cache, else built-in priors). */
+ * library (the autotuner's cache, else built-in priors: the dense schedule
+ * on tiles of 16384 starts for patterns without links, m < 2q with q <= 4,
+ * which the default q gives every m <= 7; else the segment schedule on
+ * tiles of 25600 starts). */
 typedef struct {
     int32_t segment;     /* window starts per lane; tile = 256 * segment     */
     int32_t schedule;    /* HC_SCHED_*                                        */

@@ -73,6 +73,20 @@ __device__ __forceinline__ TileResult batch_tile_q(uint32_t q, const uint32_t *t
     }
 }
 
+// Patterns without links (m < 2q, q <= 4): every window of the tile is tested
+// at once (the dense schedule); the table is not read.
+template <typename WT>
+__device__ __forceinline__ TileResult batch_dense_q(uint32_t q, const uint32_t *t32, uint32_t tb, const WT *F,
+                                                    const uint32_t *x32, const PatternView &P, uint32_t S,
+                                                    uint32_t *bm, uint32_t *misc, uint32_t &it) {
+    switch (q) {
+        case 1: return dense_tile<1, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        case 2: return dense_tile<2, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        case 3: return dense_tile<3, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        default: return dense_tile<4, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+    }
+}
+
 // Per-pattern table and bytes, staged through registers: 16 bytes per thread
 // per step (tables <= 16 KiB and patterns <= 4 KiB + padding).
 constexpr int kFStage = 4;    // up to 16 KiB of F
@@ -185,9 +199,12 @@ __global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
             const uint32_t S = uint32_t(min<uint64_t>(A.tile, starts - tile_lo));
             const PatternView P{bp.m, bp.q, bp.s, bp.mask, bp.hv};
             const uint32_t shift = bp.m - bp.q + 1u;
-            const TileResult R = shift <= 12u
-                ? batch_tile_q<WT, 4>(bp.q, t32, tb, F, x32, P, S, A.seg, bm, park, misc, it, round)
-                : batch_tile_q<WT, 1>(bp.q, t32, tb, F, x32, P, S, A.seg, bm, park, misc, it, round);
+            const TileResult R =
+                bp.q <= 4u && bp.m < 2u * bp.q
+                    ? batch_dense_q<WT>(bp.q, t32, tb, F, x32, P, S, bm, misc, it)
+                    : shift <= 12u
+                          ? batch_tile_q<WT, 4>(bp.q, t32, tb, F, x32, P, S, A.seg, bm, park, misc, it, round)
+                          : batch_tile_q<WT, 1>(bp.q, t32, tb, F, x32, P, S, A.seg, bm, park, misc, it, round);
             const uint64_t entry = A.pair_base[pair] + W.tile;
             if (R.total == 0u) {
                 if (tid == 0) A.counts[entry] = 0u;

@@ -114,8 +114,14 @@ hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req) {
     hc_launch lc{0, 0, 0, 0};
     if (req) lc = *req;
     const Tuned t = get_tuned(p.m);
-    if (lc.segment <= 0) lc.segment = t.set ? t.segment : 100;   // tile of 25600 starts
-    if (lc.schedule == HC_SCHED_AUTO) lc.schedule = t.set ? t.schedule : HC_SCHED_SEGMENT;
+    // untuned: patterns without links (m < 2q, q <= 4) take the dense
+    // schedule on tiles of 16384 starts, the others the searching loop on
+    // tiles of 25600
+    const bool nolink = p.q <= 4 && p.m < 2 * int64_t(p.q);
+    const bool dense = lc.schedule == HC_SCHED_DENSE ||
+                       (lc.schedule == HC_SCHED_AUTO && (t.set ? t.schedule == HC_SCHED_DENSE : nolink));
+    if (lc.segment <= 0) lc.segment = t.set ? t.segment : (dense ? 64 : 100);
+    if (lc.schedule == HC_SCHED_AUTO) lc.schedule = t.set ? t.schedule : (nolink ? HC_SCHED_DENSE : HC_SCHED_SEGMENT);
     if (lc.variant == HC_VARIANT_AUTO) lc.variant = t.set && t.variant ? t.variant : HC_VARIANT_HC;
     (void)n;
     return lc;
