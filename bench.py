@@ -568,18 +568,29 @@ def main():
         step(None)
     torch.cuda.synchronize()
 
+    # timed steps: back-to-back launches, events only around the whole run
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
     t_wall = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
+    for _ in range(args.steps):
+        step(None)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
-    per_launch = np.array([[ev0[k][i].elapsed_time(ev1[k][i]) for i in range(len(pats))]
-                           for k in range(args.steps)])
     ms_total = start.elapsed_time(stop)
     ms_step = ms_total / args.steps
+
+    # the same steps again with an event pair around every call (search +
+    # emit kernels): the per-call durations of the roofline and the detail
+    e_start, e_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_start.record(stream)
+    for k in range(args.steps):
+        step(k)
+    e_stop.record(stream)
+    torch.cuda.synchronize()
+    ms_step_events = e_start.elapsed_time(e_stop) / args.steps
+    per_launch = np.array([[ev0[k][i].elapsed_time(ev1[k][i]) for i in range(len(pats))]
+                           for k in range(args.steps)])
 
     cnt = counts.cpu().numpy()
     text_bytes = sum(int(texts[s].size) for (s, _, _, _) in pats)
@@ -654,6 +665,7 @@ def main():
         "config": {"workload": workload, "launches_per_step": len(pats),
                    "text_bytes_per_step": text_bytes, "occurrences_per_step": int(cnt.sum()),
                    "wall_s": round(wall, 3),
+                   "ms_per_step_with_call_events": round(ms_step_events, 3),
                    "autotune": ({"seconds": round(tune_s, 1),
                                  "choice": {f"{s_}/{m}": {"q_alpha_w": list(r["params"]),
                                                           "segment": r["launch"][0],
