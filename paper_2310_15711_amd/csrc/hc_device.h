@@ -671,9 +671,15 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
     uint16_t *bm16 = reinterpret_cast<uint16_t *>(bm);
     const uint32_t steps = (S + 15u) / 16u;
     const bool inline_check = P.m <= 4u;
-    // x's m bytes as the top m bytes of a word ending at the window end
-    const uint32_t xw = inline_check ? (x32[0] << (8u * (4u - P.m))) : 0u;
-    const uint32_t xmask = inline_check ? (0xFFFFFFFFu << (8u * (4u - P.m))) : 0u;
+    // m <= 4: byte r of window 2i sits at p0 + 4 - m + r + 2i; its pair
+    // (windows 2i, 2i + 1) is compared with x[r] in both 16-bit halves
+    uint32_t xr[4], sel[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t o = 4u - P.m + uint32_t(r);
+        sel[r] = 0x0C000C00u | o | ((o + 1u) << 16);
+        xr[r] = ((x32[0] >> (8 * r)) & 0xFFu) * 0x00010001u;
+    }
     const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
     uint32_t any = 0;
     for (uint32_t g = threadIdx.x; g < steps; g += kThreads) {
@@ -713,20 +719,29 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
             all &= nz[i];
         }
         if (all == 0x80008000u) continue;   // no window-end hash equals H_v
+        if (inline_check) {
+            // the windows are compared with x right here (every window
+            // equal to x has the hash H_v, so this is the verification of
+            // the step's candidates); df < 256 in each half
+            uint32_t df[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) df[i] = 0u;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (uint32_t(r) < P.m) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        df[i] |= __builtin_amdgcn_perm(w[(i >> 1) + 1], w[i >> 1],
+                                                       sel[r] + ((i & 1) ? 0x00020002u : 0u)) ^ xr[r];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) nz[i] = df[i] + 0x7FFF7FFFu;
+        }
         uint32_t e = 0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) e |= (~nz[i] & 0x80008000u) >> (15 - 2 * i);
         uint32_t bits = (e | (e >> 15)) & 0xFFFFu;
-        if (inline_check) {   // the window is in the word that ends it
-            uint32_t eq = 0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t word = (j & 3) ? __builtin_amdgcn_alignbyte(w[(j >> 2) + 1], w[j >> 2], j & 3)
-                                              : w[j >> 2];
-                eq |= uint32_t(((word ^ xw) & xmask) == 0u) << j;
-            }
-            bits &= eq;
-        }
         if (st0 + 16u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
         if (bits) bm16[g] = uint16_t(bits);
         any |= bits;
