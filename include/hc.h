@@ -108,7 +108,7 @@ typedef struct hc_pattern hc_pattern;   /* opaque; immutable once built      */
  * every pattern whose length falls in the same bucket (2^(b-1), 2^b]; the
  * last tuning of a bucket wins, process-wide. Candidates: q in [1, min(m,
  * 8)], (alpha, w) in {(8,8), (10,16), (11,16), (12,16), (12,32)}, the segment
- * and dense schedules, segments {64, 100, 132, 200}, and for m >= 256 the
+ * and dense schedules, segments {48, 64, 80, 100}, and for m >= 256 the
  * sparse variant with segments {512, 1024, 2048, 4096}; timed with `patterns`
  * (1..64) patterns copied from the text at fixed pseudo-random offsets.
  * out[i] (may be NULL) receives the choice for ms[i] and its median text

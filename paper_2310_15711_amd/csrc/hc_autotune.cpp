@@ -158,7 +158,7 @@ extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *m
         // phase 2: the best four with several segments, all sample patterns
         Cand best{0, 0, 0, 0, 0, HC_VARIANT_HC};
         best.ms = 1e30;
-        static const int hc_segs[4] = {64, 100, 132, 200};
+        static const int hc_segs[4] = {48, 64, 80, 100};   // larger tiles do not fit the staging
         static const int sparse_segs[4] = {512, 1024, 2048, 4096};   // the sparse tiles are larger
         for (size_t k = 0; k < std::min<size_t>(4, cs.size()) && st == HC_OK; ++k)
             for (int j = 0; j < 4; ++j) {

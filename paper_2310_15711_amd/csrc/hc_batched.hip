@@ -88,8 +88,11 @@ __device__ __forceinline__ TileResult batch_dense_q(uint32_t q, const uint32_t *
 }
 
 // Per-pattern table and bytes, staged through registers: 16 bytes per thread
-// per step (tables <= 16 KiB and patterns <= 4 KiB + padding).
-constexpr int kFStage = 4;    // up to 16 KiB of F
+// per step (patterns <= 4 KiB + padding). Only the first 8 KiB of a table
+// travel in registers (more would cost the kernel a wavefront per SIMD); the
+// rest of a larger table (up to 16 KiB) is copied when it is committed.
+constexpr int kFStage = 2;
+constexpr uint32_t kMaxBatchTable = 16384;
 struct PatStage {
     u32x4 f[kFStage];
     u32x4 x[2];
@@ -114,8 +117,8 @@ __device__ __forceinline__ void pat_issue(const uint8_t *Fs, const uint8_t *xs, 
     }
 }
 
-__device__ __forceinline__ void pat_commit(const PatStage &ps, uint8_t *F, uint8_t *x8,
-                                           uint32_t table_bytes, uint32_t x_bytes) {
+__device__ __forceinline__ void pat_commit(const PatStage &ps, const uint8_t *Fs, uint32_t p, uint8_t *F,
+                                           uint8_t *x8, uint32_t table_bytes, uint32_t x_bytes) {
     u32x4 *f = reinterpret_cast<u32x4 *>(F);
     const uint32_t nf = table_bytes / 16u;
 #pragma unroll
@@ -123,6 +126,8 @@ __device__ __forceinline__ void pat_commit(const PatStage &ps, uint8_t *F, uint8
         const uint32_t c = k * kThreads + threadIdx.x;
         if (c < nf) f[c] = ps.f[k];
     }
+    const global_u32x4 *src = (const global_u32x4 *)(Fs + uint64_t(p) * table_bytes);
+    for (uint32_t c = kFStage * kThreads + threadIdx.x; c < nf; c += kThreads) f[c] = src[c];
     u32x4 *x = reinterpret_cast<u32x4 *>(x8);
     const uint32_t nx = x_bytes / 16u;
 #pragma unroll
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
         for (uint32_t gi = W.g0; gi < W.g1; ++gi) {
             const uint32_t p = A.glist[2 * gi], pair = A.glist[2 * gi + 1];
             const BPat bp = A.pats[p];
-            pat_commit(ps, F8, x8, A.table_bytes, L.x_bytes);
+            pat_commit(ps, A.Fs, p, F8, x8, A.table_bytes, L.x_bytes);
             lds_barrier();
             if (gi + 1 < W.g1) {
                 const uint32_t pn = A.glist[2 * (gi + 1)];
@@ -453,7 +458,7 @@ hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &tab
     if ((w != 16 && w != 32) || alpha < 1 || alpha > alpha_max(w)) return HC_EINVAL;
     table_bytes = uint32_t((size_t(1) << alpha) * size_t(w / 8));
     table_bytes = std::max<uint32_t>(16, (table_bytes + 15u) & ~15u);
-    if (table_bytes > uint32_t(kFStage) * kThreads * 16u) return HC_EINVAL;   // <= 16 KiB
+    if (table_bytes > kMaxBatchTable) return HC_EINVAL;
     return HC_OK;
 }
 

@@ -382,7 +382,11 @@ __device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32, uint32
 // them to LDS. Byte g0 lands at LDS text position 16 + ((uintptr)(y + g0) & 15)
 // (returned by stage_issue). Every chunk read holds at least one byte of
 // [g0, g1), so no read leaves the pages that hold the text.
-constexpr int kStageMax = 10;   // chunks per thread: (tile + m - 1) <= 16 * 256 * kStageMax - 32
+// 16-byte chunks per thread held in registers while they travel: (tile +
+// m - 1) <= 16 * 256 * kStageMax - 32. Seven (tiles up to 27.6 K starts for
+// m = 1024) keep the kernels at 4-6 wavefronts per SIMD; ten cost each of
+// them a wavefront per SIMD, worth more than larger tiles.
+constexpr int kStageMax = 7;
 
 struct Stage {
     u32x4 r[kStageMax];

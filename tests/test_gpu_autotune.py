@@ -42,7 +42,7 @@ def test_autotune_choices_are_used_and_exact(text):
                 assert t["m"] >= 256 and sched == B.HC_SCHED_SEGMENT and seg in (512, 1024, 2048, 4096)
             else:
                 assert variant == B.HC_VARIANT_HC
-                assert sched in (B.HC_SCHED_SEGMENT, B.HC_SCHED_DENSE) and seg in (64, 100, 132, 200)
+                assert sched in (B.HC_SCHED_SEGMENT, B.HC_SCHED_DENSE) and seg in (48, 64, 80, 100)
             assert t["gbps"] > 0
         rs = np.random.default_rng(3)
         for t in tuned:
