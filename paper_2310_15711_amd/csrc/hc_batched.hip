@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
         // longest pattern of the group comes first
         const uint32_t span = A.pats[A.glist[2 * W.g0]].m;
         const uint64_t g1 = min<uint64_t>(tile_lo + A.tile + span - 1u, n_t);
-        Stage st;
+        Stage<> st;
         const uint32_t tb = stage_issue(tv.ptr, tile_lo, g1, st);
         PatStage ps;
         {

@@ -388,19 +388,24 @@ __device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32, uint32
 // them a wavefront per SIMD, worth more than larger tiles.
 constexpr int kStageMax = 7;
 
+// Dense-schedule kernels hold five (tiles up to 20 K starts): they are the
+// most VALU-bound and gain most from the extra wavefronts.
+constexpr int kStageDense = 5;
+
+template <int N = kStageMax>
 struct Stage {
-    u32x4 r[kStageMax];
+    u32x4 r[N];
     uint32_t nch;
 };
 
-__host__ __device__ inline uint32_t stage_limit(uint32_t threads) {
-    return 16u * threads * uint32_t(kStageMax) - 32u;
+__host__ __device__ inline uint32_t stage_limit(uint32_t threads, int chunks = kStageMax) {
+    return 16u * threads * uint32_t(chunks) - 32u;
 }
 
 typedef const __attribute__((address_space(1))) u32x4 global_u32x4;
 
-__device__ __forceinline__ uint32_t stage_issue(const uint8_t *y, uint64_t g0, uint64_t g1,
-                                                Stage &st) {
+template <int N>
+__device__ __forceinline__ uint32_t stage_issue(const uint8_t *y, uint64_t g0, uint64_t g1, Stage<N> &st) {
     const uint8_t *a = y + g0;
     const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(a) & 15u);
     st.nch = (mis + uint32_t(g1 - g0) + 15u) >> 4;
@@ -408,17 +413,18 @@ __device__ __forceinline__ uint32_t stage_issue(const uint8_t *y, uint64_t g0, u
     // counter and make every LDS barrier wait for this prefetch
     global_u32x4 *src = (global_u32x4 *)(a - mis);
 #pragma unroll
-    for (int k = 0; k < kStageMax; ++k) {
+    for (int k = 0; k < N; ++k) {
         const uint32_t c = k * 256u + threadIdx.x;   // 256 threads per workgroup
         if (c < st.nch) st.r[k] = __builtin_nontemporal_load(src + c);
     }
     return 16u + mis;
 }
 
-__device__ __forceinline__ void stage_commit(const Stage &st, uint8_t *lds_text) {
+template <int N>
+__device__ __forceinline__ void stage_commit(const Stage<N> &st, uint8_t *lds_text) {
     u32x4 *dst = reinterpret_cast<u32x4 *>(lds_text + 16);
 #pragma unroll
-    for (int k = 0; k < kStageMax; ++k) {
+    for (int k = 0; k < N; ++k) {
         const uint32_t c = k * 256u + threadIdx.x;   // 256 threads per workgroup
         if (c < st.nch) dst[c] = st.r[k];
     }

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     const PatternView P{A.m, uint32_t(Q), A.s, A.mask, A.hv};
 
     // ---- search phase: workgroup b takes tiles b, b + G, b + 2G, ...
-    Stage stage;
+    constexpr bool kDense = SCHED >= HC_SCHED_DENSE && SCHED < kSchedShc;
+    Stage<kDense ? kStageDense : kStageMax> stage;
     uint32_t tb = 0;
     if (blockIdx.x < A.n_tiles) {
         const uint64_t lo = uint64_t(blockIdx.x) * A.tile;
@@ -716,8 +717,16 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
         seg = std::max<uint32_t>(8, seg / 2);
         L = lds_layout(kBlock * seg, m, table_bytes, extra);
     }
-    while (kBlock * seg + m - 1u > stage_limit(kBlock) && seg > 8) seg -= 4;
-    if (L.total > di.max_lds_per_block || kBlock * seg + m - 1u > stage_limit(kBlock)) return HC_EINVAL;
+    // the dense schedule is instantiated for q <= 4 and up to 3 links per
+    // window; other patterns run the searching loop
+    int sched = shc ? kSchedShc : lc.schedule;
+    if (sched == HC_SCHED_DENSE) {
+        const int links = int(m) / pd.q - 1;
+        sched = (pd.q <= 4 && links <= 3) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;
+    }
+    const int chunks = sched >= HC_SCHED_DENSE && sched < kSchedShc ? kStageDense : kStageMax;
+    while (kBlock * seg + m - 1u > stage_limit(kBlock, chunks) && seg > 8) seg -= 4;
+    if (L.total > di.max_lds_per_block || kBlock * seg + m - 1u > stage_limit(kBlock, chunks)) return HC_EINVAL;
     L = lds_layout(kBlock * seg, m, table_bytes, extra);
     const uint32_t tile = kBlock * seg;
     const uint64_t n_tiles64 = (starts + tile - 1) / tile;
@@ -728,13 +737,6 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
     if (st != HC_OK) return st;
 
-    // the dense schedule is instantiated for q <= 4 and up to 3 links per
-    // window; other patterns run the searching loop
-    int sched = shc ? kSchedShc : lc.schedule;
-    if (sched == HC_SCHED_DENSE) {
-        const int links = int(m) / pd.q - 1;
-        sched = (pd.q <= 4 && links <= 3) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;
-    }
     KernelFn fn = pick_kernel(pd.q, pd.w, sched, lookahead_for(m - uint32_t(pd.q) + 1u));
     int per_cu = occupancy(fn, L.total);
     if (lc.wg_per_cu > 0) per_cu = std::min(per_cu, int(lc.wg_per_cu));
