@@ -262,7 +262,7 @@ void hc_batch_plan_free(hc_batch_plan *plan);
  * slot and room for 4096 positions per step (32 KiB); a budget below one
  * request's share gives HC_EINVAL. A scheduler thread admits queued requests
  * (FIFO) while the budget allows, and runs steps: one batched launch searches
- * the next 8 MiB chunk of every text that has active requests, for all of
+ * the next 64 MiB chunk of every text that has active requests, for all of
  * them. A request that arrives while others run joins at the next step and
  * finishes after one full cycle over its text. Results are the same as
  * hc_search's, whatever else is in flight.

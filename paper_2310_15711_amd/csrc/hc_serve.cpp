@@ -34,7 +34,11 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr uint64_t kServeChunk = 8ull << 20;        // text bytes per request per step
+// Text bytes per request per step. Each step costs a fixed host round trip
+// (build, upload, launch, read back), so larger chunks mean fewer steps per
+// request: measured at 8 x 128 MiB texts, 10 K req/s, p50/p99 went from
+// 4.4/7.0 ms (8 MiB) to 1.4/3.2 ms (64 MiB), 1.3/3.7 ms (128 MiB).
+constexpr uint64_t kServeChunk = 64ull << 20;
 constexpr uint32_t kXStride = uint32_t(kMaxM) + 32;  // pattern bytes per slot
 constexpr uint64_t kResultReserve = 4096;           // positions per request per step
 constexpr uint32_t kMaxSlots = 8192;

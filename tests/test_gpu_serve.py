@@ -15,7 +15,7 @@ from paper_2310_15711_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 MiB = 1 << 20
-CHUNK = 8 * MiB   # chunk of a text searched per step (hc.h)
+CHUNK = 64 * MiB   # chunk of a text searched per step (hc.h)
 
 
 def announce(*a):
