@@ -66,9 +66,11 @@ typedef struct {
  *             safe (shift agreement across the wavefront);
  *   dense     every window of the text gets the test the search loop applies
  *             (first word, then the chain of links back to the window start,
- *             then H_v), one window per lane, no shifts; the surviving
- *             windows are verified. For short shifts (m - q + 1 small), where
- *             the loop saves little, this avoids its divergence. */
+ *             then H_v), no shifts; the surviving windows are verified. For
+ *             short shifts (m - q + 1 small), where the loop saves little,
+ *             this avoids its divergence. Available for patterns without
+ *             links (m < 2q, any q) and for q <= 4 with up to 3 links per
+ *             window; other patterns run the segment schedule. */
 enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENSE = 3 };
 
 /* Searching-phase variant (no effect on results).
@@ -88,9 +90,9 @@ enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIA
 
 /* Launch shape of the search kernel. A field set to 0 is chosen by the
  * library (the autotuner's cache, else built-in priors: the dense schedule
- * on tiles of 16384 starts for patterns without links, m < 2q with q <= 4,
- * which the default q gives every m <= 7; else the segment schedule on
- * tiles of 25600 starts). */
+ * on tiles of 16384 starts for patterns without links, m < 2q, which the
+ * default q gives every m <= 7 and m = 8 over at most 4 distinct bytes;
+ * else the segment schedule on tiles of 25600 starts). */
 typedef struct {
     int32_t segment;     /* window starts per lane; tile = 256 * segment     */
     int32_t schedule;    /* HC_SCHED_*                                        */

@@ -102,7 +102,8 @@ std::vector<Cand> candidates(int64_t m) {
         for (const auto &aw : shapes) {
             if (aw[0] > alpha_max(aw[1])) continue;
             out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, 100});
-            if (q <= 4 && m / q - 1 <= 3) out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_DENSE, 100});
+            if (m < 2 * q || (q <= 4 && m / q - 1 <= 3))
+                out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_DENSE, 100});
             // long patterns: text read in place (most cache lines never fetched)
             if (m >= 256 && q >= 3)
                 out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, 1024, HC_VARIANT_SPARSE});

@@ -73,8 +73,8 @@ __device__ __forceinline__ TileResult batch_tile_q(uint32_t q, const uint32_t *t
     }
 }
 
-// Patterns without links (m < 2q, q <= 4): every window of the tile is tested
-// at once (the dense schedule); the table is not read.
+// Patterns without links (m < 2q): every window of the tile is tested at
+// once (the dense schedule); the table is not read.
 template <typename WT>
 __device__ __forceinline__ TileResult batch_dense_q(uint32_t q, const uint32_t *t32, uint32_t tb, const WT *F,
                                                     const uint32_t *x32, const PatternView &P, uint32_t S,
@@ -83,7 +83,11 @@ __device__ __forceinline__ TileResult batch_dense_q(uint32_t q, const uint32_t *
         case 1: return dense_tile<1, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
         case 2: return dense_tile<2, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
         case 3: return dense_tile<3, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
-        default: return dense_tile<4, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        case 4: return dense_tile<4, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        case 5: return dense_tile<5, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        case 6: return dense_tile<6, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        case 7: return dense_tile<7, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
+        default: return dense_tile<8, WT, 0>(t32, tb, F, x32, P, S, bm, misc, it);
     }
 }
 
@@ -138,7 +142,7 @@ __device__ __forceinline__ void pat_commit(const PatStage &ps, const uint8_t *Fs
 }
 
 template <typename WT>
-__global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void hc_batch_kernel(BatchArgs A) {
     extern __shared__ __align__(16) uint8_t lds[];
     const LdsLayout L = lds_layout(A.tile, A.max_m, A.table_bytes, 0);
     uint8_t *t8 = lds + L.text_off;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void hc_batch_kernel(BatchArgs A) {
             const PatternView P{bp.m, bp.q, bp.s, bp.mask, bp.hv};
             const uint32_t shift = bp.m - bp.q + 1u;
             const TileResult R =
-                bp.q <= 4u && bp.m < 2u * bp.q
+                bp.m < 2u * bp.q
                     ? batch_dense_q<WT>(bp.q, t32, tb, F, x32, P, S, bm, misc, it)
                     : shift <= 12u
                           ? batch_tile_q<WT, 4>(bp.q, t32, tb, F, x32, P, S, A.seg, bm, park, misc, it, round)

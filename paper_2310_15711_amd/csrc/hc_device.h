@@ -676,11 +676,14 @@ template <int Q, bool WIDE>
 __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t32, uint32_t tb,
                                                   const uint32_t *__restrict__ x32, const PatternView &P,
                                                   uint32_t S, uint32_t *bm) {
-    static_assert(Q >= 1 && Q <= 4, "dense schedule hashes 4-byte words");
+    static_assert(Q >= 1 && Q <= 8, "q-grams of at most 8 bytes");
     typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+    // the words loaded start PRE bytes before the first window end
+    constexpr int PRE = Q <= 4 ? 3 : 7;
+    constexpr int NWW = (PRE + 15) / 4 + 1;   // aligned words covering the 16 q-grams
     uint16_t *bm16 = reinterpret_cast<uint16_t *>(bm);
     const uint32_t steps = (S + 15u) / 16u;
-    const bool inline_check = P.m <= 4u;
+    const bool inline_check = Q <= 4 && P.m <= 4u;
     // m <= 4: byte r of window 2i sits at p0 + 4 - m + r + 2i; its pair
     // (windows 2i, 2i + 1) is compared with x[r] in both 16-bit halves
     uint32_t xr[4], sel[4];
@@ -696,14 +699,14 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
         const uint32_t st0 = 16u * g;
         // window st0 + j ends at LDS byte a0 + j; w[i] = bytes p0 + 4i .. p0 + 4i + 3
         const uint32_t a0 = tb + st0 + P.m - 1u;
-        const uint32_t p0 = a0 - 3u, base = p0 >> 2, sh = p0 & 3u;
-        uint32_t d[6], w[5];
+        const uint32_t p0 = a0 - uint32_t(PRE), base = p0 >> 2, sh = p0 & 3u;
+        uint32_t d[NWW + 1], w[NWW];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) d[i] = t32[base + i];
+        for (int i = 0; i <= NWW; ++i) d[i] = t32[base + i];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+        for (int i = 0; i < NWW; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
         // pair i = windows 2i (low half) and 2i + 1 (high half); byte k of
-        // their q-grams sits at p0 + (4 - Q) + k + 2i
+        // their q-grams sits at p0 + c and p0 + c + 1, c = PRE + 1 - Q + k + 2i
         u16x2 acc[8];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
@@ -712,9 +715,10 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
             for (int i = 0; i < 8; ++i) {
                 // v_perm numbers the bytes of {src0, src1} from src1's lowest;
                 // selector 0x0C yields a zero byte
-                const uint32_t o = uint32_t(4 - Q + k + 2 * (i & 1));
-                const uint32_t pr = __builtin_amdgcn_perm(w[(i >> 1) + 1], w[i >> 1],
-                                                          0x0C000C00u | o | ((o + 1u) << 16));
+                const int c = PRE + 1 - Q + k + 2 * i;
+                const int h = (c >> 2) < NWW - 2 ? (c >> 2) : NWW - 2;
+                const uint32_t o = uint32_t(c - 4 * h);
+                const uint32_t pr = __builtin_amdgcn_perm(w[h + 1], w[h], 0x0C000C00u | o | ((o + 1u) << 16));
                 const u16x2 r = __builtin_bit_cast(u16x2, pr);
                 acc[i] = k == 0 ? r : acc[i] + r * u16x2{uint16_t(mk), uint16_t(mk)};
             }

@@ -114,10 +114,9 @@ hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req) {
     hc_launch lc{0, 0, 0, 0};
     if (req) lc = *req;
     const Tuned t = get_tuned(p.m);
-    // untuned: patterns without links (m < 2q, q <= 4) take the dense
-    // schedule on tiles of 16384 starts, the others the searching loop on
-    // tiles of 25600
-    const bool nolink = p.q <= 4 && p.m < 2 * int64_t(p.q);
+    // untuned: patterns without links (m < 2q) take the dense schedule on
+    // tiles of 16384 starts, the others the searching loop on tiles of 25600
+    const bool nolink = p.m < 2 * int64_t(p.q);
     const bool dense = lc.schedule == HC_SCHED_DENSE ||
                        (lc.schedule == HC_SCHED_AUTO && (t.set ? t.schedule == HC_SCHED_DENSE : nolink));
     if (lc.segment <= 0) lc.segment = t.set ? t.segment : (dense ? 64 : 100);

@@ -146,7 +146,8 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
             w0 = R.w0;
             w1 = R.w1;
         } else if constexpr (SCHED >= HC_SCHED_DENSE) {   // dense, C = SCHED - HC_SCHED_DENSE
-            const TileResult R = dense_tile<(Q <= 4 ? Q : 4), WT, (SCHED - HC_SCHED_DENSE)>(
+            constexpr int C = SCHED - HC_SCHED_DENSE;
+            const TileResult R = dense_tile<(C == 0 || Q <= 4 ? Q : 4), WT, C>(
                 t32, tb_cur, F, x32, P, S, bm, misc, it);
             total = R.total;
             mine = R.mine;
@@ -566,9 +567,10 @@ template <int Q, typename WT>
 static KernelFn pick_sched(int sched, int K) {
     if (sched == HC_SCHED_WAVE) return hc_search_kernel<Q, WT, HC_SCHED_WAVE, 1>;
     if (sched == kSchedShc) return hc_search_kernel<Q, WT, kSchedShc, 1>;
+    // dense: one instance per number of links per window (0 for any q,
+    // 1..3 for q <= 4)
+    if (sched == HC_SCHED_DENSE + 0) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 0, 1>;
     if constexpr (Q <= 4) {
-        // dense: one instance per number of links per window (0..3)
-        if (sched == HC_SCHED_DENSE + 0) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 0, 1>;
         if (sched == HC_SCHED_DENSE + 1) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 1, 1>;
         if (sched == HC_SCHED_DENSE + 2) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 2, 1>;
         if (sched == HC_SCHED_DENSE + 3) return hc_search_kernel<Q, WT, HC_SCHED_DENSE + 3, 1>;
@@ -717,12 +719,13 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
         seg = std::max<uint32_t>(8, seg / 2);
         L = lds_layout(kBlock * seg, m, table_bytes, extra);
     }
-    // the dense schedule is instantiated for q <= 4 and up to 3 links per
-    // window; other patterns run the searching loop
+    // the dense schedule is instantiated for patterns without links (any
+    // q) and for q <= 4 with up to 3 links per window; other patterns run
+    // the searching loop
     int sched = shc ? kSchedShc : lc.schedule;
     if (sched == HC_SCHED_DENSE) {
         const int links = int(m) / pd.q - 1;
-        sched = (pd.q <= 4 && links <= 3) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;
+        sched = (links == 0 || (pd.q <= 4 && links <= 3)) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;
     }
     const int chunks = sched >= HC_SCHED_DENSE && sched < kSchedShc ? kStageDense : kStageMax;
     while (kBlock * seg + m - 1u > stage_limit(kBlock, chunks) && seg > 8) seg -= 4;

@@ -324,12 +324,12 @@ def test_variants_full_size(torch_dev, sigma):
 
 def test_dense_without_links(torch_dev):
     """Dense schedule with m < 2q (the window-end hash alone, 16-bit packed),
-    every alpha up to 16, all byte values, misaligned views."""
+    q up to 8, every alpha up to 16, all byte values, misaligned views."""
     g = np.random.default_rng(11)
     for sigma in (2, 4, 256):
         base = g.integers(0, sigma, size=300_011, dtype=np.uint8) * (255 // max(sigma - 1, 1))
-        for m in range(1, 8):
-            for q in range((m + 2) // 2, min(m, 4) + 1):
+        for m in range(1, 16):
+            for q in range((m + 2) // 2, min(m, 8) + 1):
                 for alpha, w in ((4, 8), (8, 8), (12, 16), (16, 8)):
                     off = int(g.integers(0, 4))
                     y = base[off:]
