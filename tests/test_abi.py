@@ -141,3 +141,15 @@ def test_bucket_defaults_after_reset():
         p = B.hc_preprocess(bytes((7 * i) % 256 for i in range(m)))
         info = B.hc_pattern_info(p)
         assert 1 <= info["q"] <= min(m, 8)
+
+
+def test_short_patterns_default_to_no_links():
+    """Untuned, every m <= 7 gets the smallest q with m < 2q (no links: the
+    dense schedule's single-hash test), with s = floor(alpha / q) >= 1."""
+    B.hc_autotune_reset()
+    for m in range(1, 8):
+        for x in (b"ACGTACG"[:m], bytes(range(40, 40 + m))):
+            info = B.hc_pattern_info(B.hc_preprocess(x))
+            q = info["q"]
+            assert m < 2 * q and (q == 1 or m >= 2 * (q - 1)), (m, q)
+            assert info["s"] == info["alpha"] // q >= 1
