@@ -76,6 +76,41 @@ def test_batched_random(seed, sigma, w):
     check(texts, pats, pairs, d_text, off, pos, pair_off, cap)
 
 
+@pytest.mark.parametrize("q", [5, 6, 7, 8])
+def test_batched_long_qgrams_without_links(q):
+    """Patterns of length q..2q-1 with an explicit q (no links: the dense
+    test in the batched kernel, q-grams of 5-8 bytes) next to longer ones
+    (the searching loop), one plan, tables of 8 and 16 KiB."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    g = random.Random(40 + q)
+    rs = np.random.default_rng(40 + q)
+    for sigma, alpha, w in ((4, 12, 16), (3, 12, 32)):
+        alph = np.array(g.sample(range(256), sigma), dtype=np.uint8)
+        texts = [alph[rs.integers(0, sigma, size=g.randint(1, 200_000))] for _ in range(5)]
+        pats = []
+        for _ in range(24):
+            m = g.randint(q, 2 * q - 1) if g.random() < 0.75 else g.randint(2 * q, 40)
+            t = g.choice(texts)
+            if t.size >= m and g.random() < 0.8:
+                o = g.randint(0, t.size - m)
+                pats.append(t[o:o + m].tobytes())
+            else:
+                pats.append(alph[rs.integers(0, sigma, size=m)].tobytes())
+        pairs = [(p, t) for p in range(len(pats)) for t in range(len(texts))]
+        d_text, off = pack(texts, dev)
+        total_want = sum(O.count(pats[p], texts[t]) for p, t in pairs)
+        cap = total_want + 5
+        pos = torch.full((cap,), -1, dtype=torch.int64, device=dev)
+        pair_off = torch.empty(len(pairs) + 1, dtype=torch.int64, device=dev)
+        announce("batched long q-grams", q, sigma, alpha, w, len(pairs), total_want)
+        st, total = B.hc_search_batched(d_text, off, pats, [p for p, _ in pairs], [t for _, t in pairs],
+                                        pos, pair_off, params=(q, alpha, w))
+        assert st == B.HC_OK and total == total_want
+        check(texts, pats, pairs, d_text, off, pos, pair_off, cap)
+
+
 def test_batched_overflow_and_scratch_growth():
     import torch
 
