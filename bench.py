@@ -464,7 +464,7 @@ def main():
             print(json.dumps(summarize_lds(args.lds_dir, args.summary_cmd)))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "the search runs on one GPU here (multi-GPU sharding is described, not implemented); --gpus must be 1",
+        print(json.dumps({"error": "the library searches on one GPU; sharding across GPUs is not implemented; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
