@@ -191,3 +191,33 @@ def test_plan_graph_replays_match_eager():
         assert torch.equal(pair_off, ref_off)
         assert torch.equal(pos[:total], ref_pos[:total])
         del junk
+
+
+def test_batched_workload_sample_against_oracle():
+    """The full batched workload (64 texts of log-normal length, 4096
+    patterns of log-uniform length 4..1024, about 87 K pairs) run as one plan;
+    1,200 seeded pairs compared element by element with the oracle, and the
+    plan's per-pair counts summed over those pairs."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    b = W.batched_config()
+    d_text, off = pack(b.texts, dev)
+    pp, pt = b.pairs[:, 0].copy(), b.pairs[:, 1].copy()
+    announce("batched workload", len(b.texts), len(b.patterns), len(pp))
+    plan = B.BatchPlan(d_text, off, b.patterns, pp, pt)
+    pair_off = torch.empty(len(pp) + 1, dtype=torch.int64, device=dev)
+    st, total = plan.run(torch.empty(0, dtype=torch.int64, device=dev), pair_off)
+    pos = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+    st, total2 = plan.run(pos, pair_off)
+    assert st == B.HC_OK and total2 == total
+    po = pair_off.cpu().numpy()
+    assert po[0] == 0 and po[-1] == total and np.all(np.diff(po) >= 0)
+    g = np.random.default_rng([231015711, 4, 9, 1])
+    for k in np.sort(g.choice(len(pp), size=1200, replace=False)):
+        want = O.occurrences(b.patterns[int(pp[k])], b.texts[int(pt[k])])
+        lo, hi = int(po[k]), int(po[k + 1])
+        assert hi - lo == want.size, (int(k), hi - lo, want.size)
+        assert np.array_equal(pos[lo:hi].cpu().numpy(), want), int(k)
+    del plan, d_text, pos
+    torch.cuda.empty_cache()

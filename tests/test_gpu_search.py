@@ -383,3 +383,53 @@ def test_repeated_runs_identical(torch_dev):
                 assert np.array_equal(got, want), (m, q)
             else:
                 assert np.array_equal(got, first), (m, q, rep)
+
+
+def test_threads_share_the_default_stream(torch_dev):
+    """Host threads searching at once on the default stream (the workspace of
+    that stream is shared): each call's lists equal the oracle's, also while
+    other threads' calls make the workspace grow."""
+    import threading
+
+    import torch
+
+    g = np.random.default_rng(41)
+    y = (g.integers(0, 4, size=3_000_000, dtype=np.uint8) + 65)
+    yd = to_dev(y, torch_dev)
+    torch.cuda.synchronize()
+    jobs = []
+    for t in range(4):
+        for k in range(12):
+            n = int(g.integers(1000, y.size))   # text lengths vary: tile counts grow and shrink
+            m = int(g.choice([3, 6, 16, 200]))
+            o = int(g.integers(0, n - m))
+            launch = (int(g.choice([8, 36, 100, 512])), 0,
+                      B.HC_VARIANT_SPARSE if m >= 200 and k % 2 else 0, 0)
+            jobs.append((t, n, y[o:o + m].tobytes(), launch))
+    results, errors = {}, []
+
+    def worker(t):
+        try:
+            for i, (tt, n, x, launch) in enumerate(jobs):
+                if tt != t:
+                    continue
+                p = B.hc_preprocess(x)
+                want_cap = n
+                out = torch.empty(want_cap, dtype=torch.int64, device=torch_dev)
+                cnt = torch.zeros(1, dtype=torch.int64, device=torch_dev)
+                B.hc_search_async(p, yd[:n], out, cnt, launch=launch, stream=0)
+                torch.cuda.synchronize()
+                c = int(cnt.item())
+                results[i] = out[:c].cpu().numpy()
+        except Exception as e:   # reported by the main thread
+            errors.append(repr(e))
+
+    announce("threads on the default stream", len(jobs))
+    ths = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    assert not errors, errors
+    for i, (t, n, x, launch) in enumerate(jobs):
+        assert np.array_equal(results[i], O.occurrences(x, y[:n])), (i, n, len(x), launch)

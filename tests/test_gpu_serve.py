@@ -231,3 +231,35 @@ def test_destroy_with_work_in_flight(texts):
     finally:
         srv.close()
     check(host, reqs[:20], got)
+
+
+def test_served_workload_against_oracle():
+    """Requests shaped like the served workload (four iid byte texts and four
+    order-2 Markov texts, Poisson arrivals, m log-uniform in 4..2048,
+    extracted with probability 1/2), submitted as they arrive; every one of
+    the 1,000+ requests compared with the oracle."""
+    import time
+
+    import torch
+
+    host = W.served_texts(n_each=24 * MiB)
+    dev = [torch.from_numpy(t).to("cuda:0") for t in host]
+    torch.cuda.synchronize()
+    reqs = W.request_stream(host, rate=5000.0, duration=0.22, sub=7)
+    assert len(reqs) >= 1000
+    srv = B.Server(dev, 512 * MiB)
+    announce("served workload", len(reqs))
+    t0 = time.perf_counter()
+    ids = []
+    for r in reqs:
+        ahead = t0 + r.arrival - time.perf_counter()
+        if ahead > 0:
+            time.sleep(ahead)
+        ids.append(srv.submit(r.text, r.pattern))
+    got = [srv.result(i, timeout_s=120) for i in ids]
+    srv.close()
+    for r, pos in zip(reqs, got):
+        want = O.occurrences(r.pattern, host[r.text])
+        assert np.array_equal(pos, want), (r.text, len(r.pattern), r.extracted_at)
+    del dev
+    torch.cuda.empty_cache()
