@@ -16,7 +16,9 @@
  *     pointers are host pointers.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Device work is ordered on that stream; calls on one stream serialise,
- *     calls on different streams may run concurrently.
+ *     calls on different streams may run concurrently. Several host threads
+ *     may enqueue searches on the same stream: each call's kernels are
+ *     enqueued together, never interleaved with another call's.
  *   - The caller owns every text and output buffer and keeps device buffers
  *     alive until the stream work that uses them has finished.
  *   - Text lengths are limited to n <= 2^32 - 1 bytes per text.
@@ -78,7 +80,10 @@ enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENS
  *   sentinel  SHC (Section 3.4, third optimisation): a copy of x is placed
  *             after each text tile in on-chip memory, so the loop over
  *             empty words runs without a position test (a lane's loop may
- *             run into the next lane's range before it stops);
+ *             run into the next lane's range before it stops). Kept for
+ *             reference and parity only: with many lanes per tile the
+ *             overrun costs far more than the saved test, so it is slower
+ *             than `hc` everywhere and the library never chooses it;
  *   sparse    for long patterns: no tile is staged; each lane reads the
  *             q-grams it hashes (and the windows it verifies) in place, so
  *             only the cache lines that hold them are fetched; long chain
@@ -216,7 +221,10 @@ hc_status hc_search_async(const hc_pattern *p, const uint8_t *d_y, int64_t n,
  * d_pos[d_pair_off[k] .. d_pair_off[k+1]) ascending; d_pair_off has
  * n_pairs + 1 entries. *total (host) = all occurrences. total > cap ->
  * HC_EOVERFLOW; then d_pair_off still holds the full offsets but d_pos holds
- * only positions whose slot is < cap. Synchronises `stream`.
+ * only positions whose slot is < cap. Synchronises `stream`. Positions are
+ * gathered in a device scratch buffer first (grown when a run needs more,
+ * then the run is repeated once); a batch that would need 2^32 - 1 or more
+ * scratch positions gives HC_ENOMEM (split it).
  *   params  NULL = q chosen per pattern (autotuner / priors), alpha = 12, w = 16.
  */
 typedef struct {

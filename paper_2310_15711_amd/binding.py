@@ -112,8 +112,12 @@ def _check(status: int, what: str, ok=(HC_OK,)):
 
 
 def _stream_ptr(stream) -> Optional[int]:
+    """hipStream_t of a torch stream (None = torch's current stream); an int is
+    taken as a raw stream handle (0 = the default stream)."""
     import torch
 
+    if isinstance(stream, int):
+        return stream or None
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream) or None

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "hc_internal.h"
 
@@ -21,16 +22,20 @@ struct DeviceInfo {
 // Info for the current device (cached per device id).
 const DeviceInfo &device_info();
 
-// Launch workspace of one (device, stream): the grid-barrier control block and
-// per-tile results of the search phase (counts, short position slots, spilled
-// bitmaps). Calls on one stream serialise, so one workspace per stream is never
-// used by two launches at once.
+// Launch workspace of one (device, stream): per-tile results of the search
+// phase (counts, short position slots, spilled bitmaps), written by the
+// search kernel and read by the emit kernel that follows it on the stream.
+// Work on one stream runs in order, so the pair of one call finishes before
+// the next call's search kernel starts; host threads that enqueue on the same
+// stream hold the workspace's lock from the lookup until both kernels of their
+// call are enqueued, so the pairs of two calls never interleave and a
+// regrowth never frees buffers that a call has already taken.
 // Occurrences a tile keeps as a list of tile-relative starts; denser tiles
 // keep their bitmap.
 constexpr uint32_t kSlot = 128;
 
 struct Workspace {
-    void *ctl = nullptr;          // control words (work tickets), zero-initialised
+    std::mutex mu;                // held by the call that enqueues on this stream
     uint32_t *counts = nullptr;   // tiles_cap entries
     uint32_t *slots = nullptr;    // tiles_cap * kSlot entries
     uint32_t *spill = nullptr;    // spill_words_cap entries
@@ -38,14 +43,32 @@ struct Workspace {
     uint64_t spill_words_cap = 0;
 };
 
-hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out);
+// Workspace of (current device, stream) with room for `tiles` tiles of `tile`
+// window starts; returns with *lock holding the workspace's mutex.
+hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out,
+                        std::unique_lock<std::mutex> *lock);
 
-// Device copies of a pattern's F (packed w-bit words) and x on the current device.
+// Per-tile results of one search call (counts, slot lists, spilled bitmaps).
+struct TileScratch {
+    uint32_t *counts = nullptr;
+    uint32_t *slots = nullptr;
+    uint32_t *spill = nullptr;
+};
+
+// Device copies of a pattern's F (packed w-bit words) and x on the current
+// device, uploaded on first use.
 hc_status pattern_on_device(hc_pattern *p, const DeviceCopy **out);
+// The same without uploading: null when the pattern has no copy on the
+// current device yet.
+const DeviceCopy *pattern_resident(hc_pattern *p);
 
+// Enqueues one search call (search kernel + emit kernel) on `stream`. The
+// per-tile results go to the stream's workspace, or, when `fixed` is set, to
+// that device region of `fixed_bytes` bytes (HC_EINVAL when the call needs
+// more; nothing is allocated then).
 hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
                         int64_t *d_out, int64_t cap, int64_t *d_count, const hc_launch &lc,
-                        hipStream_t stream);
+                        hipStream_t stream, void *fixed = nullptr, uint64_t fixed_bytes = 0);
 
 // Launch shape chosen for a pattern when the caller leaves fields at 0.
 hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req);

@@ -34,20 +34,23 @@ const DeviceInfo &device_info() {
     return cache.emplace(dev, di).first->second;
 }
 
-hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out) {
+hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out,
+                        std::unique_lock<std::mutex> *lock) {
     static std::mutex mu;
     static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> spaces;
     const DeviceInfo &di = device_info();
     if (!di.ok) return HC_EHIP;
-    std::lock_guard<std::mutex> g(mu);
-    auto &slot = spaces[std::make_pair(di.device, stream)];
-    if (!slot) {
-        slot.reset(new (std::nothrow) Workspace());
-        if (!slot) return HC_ENOMEM;
-        if (hipMalloc(&slot->ctl, 64) != hipSuccess) return HC_ENOMEM;
-        HC_CHECK_HIP(hipMemset(slot->ctl, 0, 64));   // work tickets of dynamically dealt kernels
+    Workspace *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto &slot = spaces[std::make_pair(di.device, stream)];
+        if (!slot) {
+            slot.reset(new (std::nothrow) Workspace());
+            if (!slot) return HC_ENOMEM;
+        }
+        ws = slot.get();   // entries are never removed: the address stays valid
     }
-    Workspace *ws = slot.get();
+    std::unique_lock<std::mutex> held(ws->mu);
     const uint64_t spill_words = uint64_t(tiles) * (tile / 32u);
     if (ws->tiles_cap < tiles || ws->spill_words_cap < spill_words) {
         // earlier launches on this stream may still use the old buffers
@@ -75,6 +78,7 @@ hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Works
         }
     }
     *out = ws;
+    *lock = std::move(held);
     return HC_OK;
 }
 
@@ -108,6 +112,15 @@ hc_status pattern_on_device(hc_pattern *p, const DeviceCopy **out) {
     p->dev.push_back(dc);
     *out = &p->dev.back();
     return HC_OK;
+}
+
+const DeviceCopy *pattern_resident(hc_pattern *p) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(p->mu);
+    for (const DeviceCopy &dc : p->dev)
+        if (dc.device == dev) return &dc;
+    return nullptr;
 }
 
 hc_launch choose_launch(const PatternData &p, int64_t n, const hc_launch *req) {

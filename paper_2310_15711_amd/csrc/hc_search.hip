@@ -641,14 +641,44 @@ static KernelFn pick_sparse(int q, int w) {
     }
 }
 
-static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const Workspace *ws,
+static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const TileScratch &ts,
                              int64_t *d_out, int64_t cap, int64_t *d_count, hipStream_t stream);
+
+// Layout of the per-tile results of one call in one region: counts, then
+// the slot lists, then the spilled bitmaps, each part 256-byte aligned.
+// Returns the region's size in bytes.
+static uint64_t tile_scratch_layout(uint32_t n_tiles, uint32_t tile, uint64_t *slots_off, uint64_t *spill_off) {
+    const uint64_t t = std::max<uint32_t>(n_tiles, 1u);
+    *slots_off = (t * 4u + 255u) & ~uint64_t(255);
+    *spill_off = *slots_off + ((t * kSlot * 4u + 255u) & ~uint64_t(255));
+    return *spill_off + t * (tile / 32u) * 4u;
+}
+
+// Per-tile results of one call: the stream's workspace (locked in *held until
+// the call's two kernels are enqueued), or, when `fixed` is set, the caller's
+// region of `fixed_bytes` bytes (HC_EINVAL when the call needs more).
+static hc_status tile_scratch(hipStream_t stream, uint32_t n_tiles, uint32_t tile, void *fixed,
+                              uint64_t fixed_bytes, TileScratch *ts, std::unique_lock<std::mutex> *held) {
+    if (fixed) {
+        uint64_t so = 0, po = 0;
+        if (tile_scratch_layout(n_tiles, tile, &so, &po) > fixed_bytes) return HC_EINVAL;
+        uint8_t *b = static_cast<uint8_t *>(fixed);
+        *ts = TileScratch{reinterpret_cast<uint32_t *>(b), reinterpret_cast<uint32_t *>(b + so),
+                          reinterpret_cast<uint32_t *>(b + po)};
+        return HC_OK;
+    }
+    Workspace *ws = nullptr;
+    const hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1u), tile, &ws, held);
+    if (st != HC_OK) return st;
+    *ts = TileScratch{ws->counts, ws->slots, ws->spill};
+    return HC_OK;
+}
 
 // Sparse variant: tiles of 256 * segment window starts (segment 0 = 1024),
 // no text staging; the same emit kernel as the streaming path.
 static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
                                int64_t *d_out, int64_t cap, int64_t *d_count, const hc_launch &lc,
-                               hipStream_t stream) {
+                               hipStream_t stream, void *fixed, uint64_t fixed_bytes) {
     const PatternData &pd = p->data;
     const DeviceInfo &di = device_info();
     const uint32_t m = uint32_t(pd.m);
@@ -666,8 +696,9 @@ static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const 
     const uint64_t n_tiles64 = (starts + tile - 1) / tile;
     if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
     const uint32_t n_tiles = uint32_t(n_tiles64);
-    Workspace *ws = nullptr;
-    hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
+    TileScratch ts;
+    std::unique_lock<std::mutex> held;   // until both kernels are enqueued
+    hc_status st = tile_scratch(stream, n_tiles, tile, fixed, fixed_bytes, &ts, &held);
     if (st != HC_OK) return st;
     KernelFn fn = pick_sparse(pd.q, pd.w);
     int per_cu = occupancy(fn, L.total);
@@ -691,26 +722,27 @@ static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const 
     A.out = d_out;
     A.cap = cap;
     A.d_count = d_count;
-    A.counts = ws->counts;
-    A.slots = ws->slots;
-    A.spill = ws->spill;
+    A.counts = ts.counts;
+    A.slots = ts.slots;
+    A.spill = ts.spill;
     if (n_tiles > 0) {
         hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
         if (hipGetLastError() != hipSuccess) return HC_EHIP;
     }
-    return launch_emit(n_tiles, tile, starts, ws, d_out, cap, d_count, stream);
+    return launch_emit(n_tiles, tile, starts, ts, d_out, cap, d_count, stream);
 }
 
 hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
                         int64_t *d_out, int64_t cap, int64_t *d_count, const hc_launch &lc,
-                        hipStream_t stream) {
+                        hipStream_t stream, void *fixed, uint64_t fixed_bytes) {
     const PatternData &pd = p->data;
     const DeviceInfo &di = device_info();
     const uint32_t m = uint32_t(pd.m);
     const uint32_t table_bytes = uint32_t(pd.F.size() * (pd.w / 8));
     const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
 
-    if (lc.variant == HC_VARIANT_SPARSE) return launch_sparse(p, dc, d_y, n, d_out, cap, d_count, lc, stream);
+    if (lc.variant == HC_VARIANT_SPARSE)
+        return launch_sparse(p, dc, d_y, n, d_out, cap, d_count, lc, stream, fixed, fixed_bytes);
     const bool shc = lc.variant == HC_VARIANT_SENTINEL;
     const uint32_t extra = shc ? m : 0u;   // room for the sentinel copy of x
     uint32_t seg = std::min<uint32_t>(uint32_t(lc.segment), 256u);
@@ -736,8 +768,9 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
     const uint32_t n_tiles = uint32_t(n_tiles64);
 
-    Workspace *ws = nullptr;
-    hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1), tile, &ws);
+    TileScratch ts;
+    std::unique_lock<std::mutex> held;   // until both kernels are enqueued
+    hc_status st = tile_scratch(stream, n_tiles, tile, fixed, fixed_bytes, &ts, &held);
     if (st != HC_OK) return st;
 
     KernelFn fn = pick_kernel(pd.q, pd.w, sched, lookahead_for(m - uint32_t(pd.q) + 1u));
@@ -763,16 +796,16 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     A.out = d_out;
     A.cap = cap;
     A.d_count = d_count;
-    A.counts = ws->counts;
-    A.slots = ws->slots;
-    A.spill = ws->spill;
+    A.counts = ts.counts;
+    A.slots = ts.slots;
+    A.spill = ts.spill;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
     if (hipGetLastError() != hipSuccess) return HC_EHIP;
 
-    return launch_emit(n_tiles, tile, starts, ws, d_out, cap, d_count, stream);
+    return launch_emit(n_tiles, tile, starts, ts, d_out, cap, d_count, stream);
 }
 
-static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const Workspace *ws,
+static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const TileScratch &ts,
                              int64_t *d_out, int64_t cap, int64_t *d_count, hipStream_t stream) {
     const DeviceInfo &di = device_info();
     EmitArgs E;
@@ -784,9 +817,9 @@ static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, c
         std::min<uint32_t>(std::max<uint32_t>(n_tiles, 1), uint32_t(di.cus) * kEmitPerCu));
     E.per = (n_tiles + emit_grid - 1) / emit_grid;
     E.starts = starts;
-    E.counts = ws->counts;
-    E.slots = ws->slots;
-    E.spill = ws->spill;
+    E.counts = ts.counts;
+    E.slots = ts.slots;
+    E.spill = ts.spill;
     E.out = d_out;
     E.cap = cap;
     E.d_count = d_count;
