@@ -15,6 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhc.so")
+LOADGEN = os.path.join(PKG, "libhc_loadgen.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -68,6 +69,12 @@ def build(force: bool = True, jobs: int | None = None) -> str:
     subprocess.check_call([HIPCC, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp,
                            "-lpthread"])
     os.replace(tmp, LIB)
+    # the benchmark's load generator: a small host library on top of libhc
+    gen_tmp = LOADGEN + ".tmp"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-I", INCLUDE,
+                           os.path.join(CSRC, "hc_loadgen.cpp"), "-o", gen_tmp, "-L", PKG, "-lhc",
+                           "-Wl,-rpath,$ORIGIN", "-lpthread"])
+    os.replace(gen_tmp, LOADGEN)
     return LIB
 
 

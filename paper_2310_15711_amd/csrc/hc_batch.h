@@ -59,6 +59,7 @@ struct BatchDev {
     const uint8_t *xs = nullptr;   // pattern bytes at BPat::x_off
     size_t Fs_bytes = 0, xs_bytes = 0;
     hipError_t last_error = hipSuccess;   // of the last batch_enqueue
+    const BPat *pats_dev = nullptr;       // resident descriptors (then `pats` is not uploaded)
     DeviceBuf views, pats, items, glist, pair_base, counts, toff, temp, ctl, tot, bsum, grand;
 };
 
@@ -105,9 +106,14 @@ hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pai
 // After a run reported scratch overflow: room for `total` positions.
 hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total);
 
-// Copies n staged (table, padded bytes) entries into pool slots d_slots[i].
+// Copies n staged (table, padded bytes, descriptor) entries into pool slots
+// d_slots[i] of the tables, the pattern bytes and the descriptors.
 hc_status scatter_patterns(const uint8_t *d_src, const uint32_t *d_slots, uint32_t n, uint32_t table_bytes,
-                           uint32_t x_stride, uint8_t *Fpool, uint8_t *xpool, hipStream_t s);
+                           uint32_t x_stride, uint8_t *Fpool, uint8_t *xpool, BPat *pats, hipStream_t s);
+
+// Only the copy of the positions into d_pos (after a run whose scratch held
+// every position but whose output capacity was too small).
+hc_status batch_emit(BatchDev &D, int64_t *d_pos, int64_t cap, const int64_t *d_pair_off, hipStream_t s);
 
 constexpr uint32_t kBatchGroup = 128;   // patterns searched per staged tile
 

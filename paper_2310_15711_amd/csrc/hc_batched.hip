@@ -46,6 +46,7 @@ struct BatchArgs {
 };
 
 constexpr uint32_t kChunk = 8192;  // scratch positions reserved per atomic
+constexpr uint64_t kMaxScratch = 0xFFFFFFFFull;   // scratch positions addressable by 32-bit offsets
 
 template <typename WT, int Q, int K>
 __device__ __forceinline__ TileResult batch_tile(const uint32_t *t32, uint32_t tb, const WT *F,
@@ -403,18 +404,23 @@ __global__ __launch_bounds__(256) void hc_pair_emit(const uint64_t *pair_base, u
 }
 
 // Copies n staged patterns into their pool slots: entry i (stride
-// table_bytes + x_stride bytes, both multiples of 16) holds a table and the
-// padded pattern bytes of slot slots[i]. One workgroup per entry.
+// table_bytes + x_stride + sizeof(BPat) bytes, all multiples of 16) holds a
+// table, the padded pattern bytes and the descriptor of slot slots[i]. One
+// workgroup per entry.
 __global__ __launch_bounds__(256) void hc_scatter_patterns(const uint8_t *src, const uint32_t *slots, uint32_t n,
                                                            uint32_t table_bytes, uint32_t x_stride, uint8_t *Fpool,
-                                                           uint8_t *xpool) {
+                                                           uint8_t *xpool, BPat *pats) {
     const uint32_t i = blockIdx.x;
     if (i >= n) return;
-    const uint4 *e = reinterpret_cast<const uint4 *>(src + uint64_t(i) * (table_bytes + x_stride));
+    const uint32_t stride = table_bytes + x_stride + uint32_t(sizeof(BPat));
+    const uint4 *e = reinterpret_cast<const uint4 *>(src + uint64_t(i) * stride);
     uint4 *f = reinterpret_cast<uint4 *>(Fpool + uint64_t(slots[i]) * table_bytes);
     uint4 *x = reinterpret_cast<uint4 *>(xpool + uint64_t(slots[i]) * x_stride);
+    uint4 *d = reinterpret_cast<uint4 *>(pats + slots[i]);
     for (uint32_t k = threadIdx.x; k < table_bytes / 16u; k += blockDim.x) f[k] = e[k];
     for (uint32_t k = threadIdx.x; k < x_stride / 16u; k += blockDim.x) x[k] = e[table_bytes / 16u + k];
+    for (uint32_t k = threadIdx.x; k < sizeof(BPat) / 16u; k += blockDim.x)
+        d[k] = e[(table_bytes + x_stride) / 16u + k];
 }
 
 __global__ void hc_batch_reset(unsigned long long *ctl) {
@@ -636,7 +642,7 @@ hc_status batch_upload(const BatchHost &H, BatchDev &D, hipStream_t s) {
     D.n_items = uint32_t(H.items.size());
     D.n_entries = H.pair_base.back();
     if ((st = D.views.upload(H.views.data(), H.views.size() * sizeof(TextView), s)) != HC_OK) return st;
-    if ((st = D.pats.upload(H.pats.data(), H.pats.size() * sizeof(BPat), s)) != HC_OK) return st;
+    if (!D.pats_dev && (st = D.pats.upload(H.pats.data(), H.pats.size() * sizeof(BPat), s)) != HC_OK) return st;
     if ((st = D.items.upload(H.items.data(), H.items.size() * sizeof(BItem), s)) != HC_OK) return st;
     if ((st = D.glist.upload(H.glist.data(), H.glist.size() * 4, s)) != HC_OK) return st;
     if ((st = D.pair_base.upload(H.pair_base.data(), H.pair_base.size() * 8, s)) != HC_OK) return st;
@@ -653,14 +659,15 @@ hc_status batch_upload(const BatchHost &H, BatchDev &D, hipStream_t s) {
 
 hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pair_off, hipStream_t s) {
     // every buffer the kernels read must be in place
-    if (D.n_items > 0 && (!D.Fs || !D.xs || !D.views.p || !D.pats.p || !D.items.p || !D.glist.p))
+    const BPat *pats = D.pats_dev ? D.pats_dev : D.pats.as<BPat>();
+    if (D.n_items > 0 && (!D.Fs || !D.xs || !D.views.p || !pats || !D.items.p || !D.glist.p))
         return HC_EINVAL;
     if (!D.ctl.p || !D.pair_base.p || !D.temp.p || (D.n_pairs > 0 && (!D.tot.p || !D.counts.p || !D.toff.p)))
         return HC_EINVAL;
     hipLaunchKernelGGL(hc_batch_reset, dim3(1), dim3(64), 0, s, D.ctl.as<unsigned long long>());
     BatchArgs A;
     A.texts = D.views.as<TextView>();
-    A.pats = D.pats.as<BPat>();
+    A.pats = pats;
     A.xs = D.xs;
     A.Fs = D.Fs;
     A.items = D.items.as<BItem>();
@@ -704,11 +711,20 @@ hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pai
 }
 
 hc_status scatter_patterns(const uint8_t *d_src, const uint32_t *d_slots, uint32_t n, uint32_t table_bytes,
-                           uint32_t x_stride, uint8_t *Fpool, uint8_t *xpool, hipStream_t s) {
+                           uint32_t x_stride, uint8_t *Fpool, uint8_t *xpool, BPat *pats, hipStream_t s) {
     if (n == 0) return HC_OK;
-    if (table_bytes % 16u || x_stride % 16u) return HC_EINVAL;
+    if (table_bytes % 16u || x_stride % 16u || sizeof(BPat) % 16u) return HC_EINVAL;
     hipLaunchKernelGGL(hc_scatter_patterns, dim3(n), dim3(256), 0, s, d_src, d_slots, n, table_bytes, x_stride,
-                       Fpool, xpool);
+                       Fpool, xpool, pats);
+    return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
+}
+
+hc_status batch_emit(BatchDev &D, int64_t *d_pos, int64_t cap, const int64_t *d_pair_off, hipStream_t s) {
+    if (D.n_pairs == 0 || cap <= 0) return HC_OK;
+    const uint32_t pgrid = uint32_t((uint64_t(D.n_pairs) * kWave + 255u) / 256u);
+    hipLaunchKernelGGL(hc_pair_emit, dim3(pgrid), dim3(256), 0, s, D.pair_base.as<uint64_t>(),
+                       uint64_t(D.n_pairs), D.counts.as<uint32_t>(), D.toff.as<uint32_t>(),
+                       D.temp.as<int64_t>(), d_pair_off, d_pos, cap, D.ctl.as<unsigned long long>());
     return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
 }
 
@@ -719,6 +735,10 @@ hc_status batch_grow_scratch(BatchDev &D, uint64_t reserved, uint64_t total) {
     // every workgroup ends with at most one chunk partly used: a run never
     // reserves more than 2 * total + grid * kChunk.
     const uint64_t need = std::max<uint64_t>(reserved, 2 * total + uint64_t(D.grid + 16u) * kChunk);
+    // scratch offsets are stored as 32-bit values (0xFFFFFFFF marks an entry
+    // that did not fit): a capacity below 2^32 - 1 keeps every stored offset
+    // exact
+    if (need >= kMaxScratch) return HC_ENOMEM;
     if (D.temp.ensure(need * 8) != HC_OK) return HC_ENOMEM;
     D.scratch_cap = need;
     return HC_OK;
@@ -820,7 +840,10 @@ hc_status hc_batch_plan_run(hc_batch_plan *P, int64_t *d_pos, int64_t cap, int64
     if (!P || !total || !d_pair_off || cap < 0 || (cap > 0 && !d_pos)) return HC_EINVAL;
     *total = 0;
     hipStream_t s = hipStream_t(stream);
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    // a second run, with the scratch grown to the bound of batch_grow_scratch
+    // for the total the first run counted, always fits; a third is never
+    // needed, and a second run that still falls short is reported as an error
+    for (int attempt = 0; attempt < 2; ++attempt) {
         // (re)build the graph for these buffers
         if (!P->exec || P->g_pos != d_pos || P->g_off != d_pair_off || P->g_cap != cap || P->g_stream != s) {
             P->drop_graph();

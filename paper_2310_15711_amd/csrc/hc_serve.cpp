@@ -8,14 +8,21 @@
 // starts at the cursor and is complete after one full cycle over its text;
 // its positions come in two ascending runs (from its first chunk to the end
 // of the text, then from the start) that are rotated into order at the end.
-// New requests are admitted between steps while a pattern slot and the
-// device-memory budget allow; the others wait in FIFO order.
+// New requests are admitted whenever a step is built, while a pattern slot and
+// the device-memory budget allow; the others wait in FIFO order.
+//
+// Steps are pipelined: each has its own work list, result buffers and host
+// staging (a Step), and up to kSteps of them are in flight on the server's
+// stream. While the device runs step k + 1, the host reads back step k's
+// counts, copies its positions on a second stream and hands them to the
+// requests, then builds and enqueues step k + 2. Results are taken in step
+// order, so every request sees its chunks in order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
-#include <cstdio>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -34,14 +41,14 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Text bytes per request per step. Each step costs a fixed host round trip
-// (build, upload, launch, read back), so larger chunks mean fewer steps per
-// request: measured at 8 x 128 MiB texts, 10 K req/s, p50/p99 went from
-// 4.4/7.0 ms (8 MiB) to 1.4/3.2 ms (64 MiB), 1.3/3.7 ms (128 MiB).
+// Text bytes per request per step. Larger chunks mean fewer steps (each with
+// a fixed host cost) per request; smaller ones a shorter wait for a request
+// that arrives while a step runs.
 constexpr uint64_t kServeChunk = 64ull << 20;
 constexpr uint32_t kXStride = uint32_t(kMaxM) + 32;  // pattern bytes per slot
 constexpr uint64_t kResultReserve = 4096;           // positions per request per step
 constexpr uint32_t kMaxSlots = 8192;
+constexpr int kSteps = 2;                           // steps in flight
 
 struct Request {
     uint64_t id = 0;
@@ -50,13 +57,15 @@ struct Request {
     BPat bp{};
     std::vector<uint8_t> F;        // packed table
     Clock::time_point t_submit;
-    // running state
+    // scheduler state
     int32_t slot = -1;
-    uint64_t chunks_left = 0;
+    uint64_t to_issue = 0;         // chunks not yet put into a step
+    uint64_t to_take = 0;          // chunks whose positions are not yet taken
+    bool started = false;          // some chunk was put into a step
     size_t wrap_at = 0;            // positions gathered before the cursor wrapped
     bool wrapped = false;
     std::vector<int64_t> pos;
-    bool done = false;
+    bool done = false;             // set under the server lock once pos is final
     hc_status status = HC_OK;
 };
 
@@ -65,6 +74,52 @@ struct Text {
     uint64_t n = 0;
     uint64_t chunks = 0;
     uint64_t cursor = 0;           // next chunk to search
+};
+
+// Pinned host array that only grows.
+template <typename T>
+struct Pinned {
+    T *p = nullptr;
+    size_t cap = 0;
+    Pinned() = default;
+    Pinned(const Pinned &) = delete;
+    Pinned &operator=(const Pinned &) = delete;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+    hc_status ensure(size_t n) {
+        if (cap >= n && p) return HC_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t c = std::max<size_t>(n, 1024);
+        if (hipHostMalloc(reinterpret_cast<void **>(&p), c * sizeof(T), hipHostMallocDefault) != hipSuccess)
+            return HC_ENOMEM;
+        cap = c;
+        return HC_OK;
+    }
+};
+
+// One step's state. Owned by the scheduler thread; reused once its results
+// have been taken (then none of its buffers is read by the device any more).
+struct Step {
+    BatchDev D;
+    BatchHost H;
+    DeviceBuf d_pos, d_off, d_up, d_up_slots;
+    Pinned<int64_t> h_pos, h_off;
+    Pinned<unsigned long long> h_ctl;
+    Pinned<uint8_t> h_up;
+    Pinned<uint32_t> h_up_slots;
+    std::vector<std::shared_ptr<Request>> members;   // pair order
+    std::vector<uint64_t> base;                      // per member: text offset of its chunk
+    std::vector<uint8_t> wraps;                      // per member: chunk 0 after earlier chunks
+    int64_t cap = 0;
+    uint64_t bytes = 0;                              // text bytes searched (over members)
+    hipEvent_t counted = nullptr, copied = nullptr;
+    ~Step() {
+        if (counted) (void)hipEventDestroy(counted);
+        if (copied) (void)hipEventDestroy(copied);
+    }
 };
 
 }  // namespace
@@ -82,14 +137,10 @@ struct hc_server {
     uint32_t slots = 0;
 
     // device state (scheduler thread only, after creation)
-    hipStream_t stream = nullptr;
-    BatchDev D;
-    DeviceBuf Fpool, xpool, d_pos, d_off;
-    int64_t *h_pos = nullptr;   // pinned
-    size_t h_pos_cap = 0;
-    int64_t *h_off = nullptr;   // pinned
-    size_t h_off_cap = 0;
-    unsigned long long *h_ctl = nullptr;   // pinned, 4 words
+    hipStream_t stream = nullptr;     // steps, in order
+    hipStream_t copy_stream = nullptr;   // positions of finished steps
+    DeviceBuf Fpool, xpool, patpool;
+    Step steps[kSteps];
 
     // shared state
     std::mutex mu;
@@ -108,23 +159,14 @@ struct hc_server {
     std::thread worker;
 
     ~hc_server() {
-        if (h_up) (void)hipHostFree(h_up);
-        if (h_pos) (void)hipHostFree(h_pos);
-        if (h_off) (void)hipHostFree(h_off);
-        if (h_ctl) (void)hipHostFree(h_ctl);
         if (stream) (void)hipStreamDestroy(stream);
+        if (copy_stream) (void)hipStreamDestroy(copy_stream);
     }
 
-    hc_status pinned(int64_t *&p, size_t &cap, size_t need) {
-        if (cap >= need && p) return HC_OK;
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-        cap = 0;
-        const size_t n = std::max<size_t>(need, 1024);
-        if (hipHostMalloc(reinterpret_cast<void **>(&p), n * 8, hipHostMallocDefault) != hipSuccess)
-            return HC_ENOMEM;
-        cap = n;
-        return HC_OK;
+    void complete(Request &r, Clock::time_point now) {   // lock held
+        r.done = true;
+        done_q.push_back(r.id);
+        lat_us.push_back(std::chrono::duration<double, std::micro>(now - r.t_submit).count());
     }
 
     // Admits pending requests while slots and budget allow (lock held).
@@ -134,9 +176,7 @@ struct hc_server {
             const Text &t = texts[r->text];
             if (t.n < r->x.size()) {   // no window fits: complete at once
                 pending.pop_front();
-                r->done = true;
-                done_q.push_back(r->id);
-                lat_us.push_back(std::chrono::duration<double, std::micro>(Clock::now() - r->t_submit).count());
+                complete(*r, Clock::now());
                 continue;
             }
             if (used_bytes + per_request > budget) break;
@@ -149,7 +189,7 @@ struct hc_server {
             if (slot < 0) break;
             pending.pop_front();
             r->slot = slot;
-            r->chunks_left = t.chunks;
+            r->to_issue = r->to_take = t.chunks;
             r->bp.x_off = uint32_t(slot) * kXStride;
             active[slot] = r;
             used_bytes += per_request;
@@ -157,148 +197,196 @@ struct hc_server {
         }
     }
 
-    hc_status step(std::vector<std::shared_ptr<Request>> &members, uint64_t &bytes);
-    hc_status upload(const std::vector<std::shared_ptr<Request>> &reqs);
-
-    // staging of newly admitted patterns: one copy and one scatter per step
-    uint8_t *h_up = nullptr;   // pinned
-    size_t h_up_cap = 0;
-    DeviceBuf d_up, d_up_slots;
+    bool build(Step &S, std::vector<std::shared_ptr<Request>> &uploads, bool may_wait);
+    hc_status enqueue(Step &S, const std::vector<std::shared_ptr<Request>> &uploads);
+    hc_status collect(Step &S);
+    void finish(Step &S, hc_status st);
     void run();
 };
 
-// Tables and bytes of newly admitted requests into their slots: packed in
-// pinned memory, copied once, scattered by one kernel. The step that follows
-// synchronises the stream before the staging buffer is reused.
-hc_status hc_server::upload(const std::vector<std::shared_ptr<Request>> &reqs) {
-    const size_t entry = size_t(table_bytes) + kXStride, need = entry * reqs.size();
-    if (h_up_cap < need) {
-        if (h_up) (void)hipHostFree(h_up);
-        h_up = nullptr;
-        h_up_cap = 0;
-        if (hipHostMalloc(reinterpret_cast<void **>(&h_up), need, hipHostMallocDefault) != hipSuccess)
-            return HC_ENOMEM;
-        h_up_cap = need;
-    }
-    std::vector<uint32_t> slot(reqs.size());
-    for (size_t i = 0; i < reqs.size(); ++i) {
-        uint8_t *e = h_up + i * entry;
-        std::memcpy(e, reqs[i]->F.data(), table_bytes);
-        std::memset(e + table_bytes, 0, kXStride);
-        std::memcpy(e + table_bytes, reqs[i]->x.data(), reqs[i]->x.size());
-        slot[i] = uint32_t(reqs[i]->slot);
-    }
-    if (d_up.ensure(need) != HC_OK) return HC_ENOMEM;
-    if (hipMemcpyAsync(d_up.p, h_up, need, hipMemcpyHostToDevice, stream) != hipSuccess) return HC_EHIP;
-    hc_status st = d_up_slots.upload(slot.data(), slot.size() * 4, stream);
-    if (st != HC_OK) return st;
-    // the slot list is pageable: wait for its copy before the vector goes
-    if (hipStreamSynchronize(stream) != hipSuccess) return HC_EHIP;
-    return scatter_patterns(d_up.as<uint8_t>(), d_up_slots.as<uint32_t>(), uint32_t(reqs.size()), table_bytes,
-                            kXStride, Fpool.as<uint8_t>(), xpool.as<uint8_t>(), stream);
-}
-
-// One step: the current chunk of every text with active requests, for all
-// of them (`members`, in pair order); their positions are appended.
-hc_status hc_server::step(std::vector<std::shared_ptr<Request>> &members, uint64_t &bytes) {
-    auto fail = [&](const char *where, hc_status st) {
-        const hipError_t e = hipGetLastError();
-        std::fprintf(stderr, "hc_serve: step failed in %s: %s (HIP: %s; launch: %s)\n", where, hc_strerror(st),
-                     hipGetErrorString(e), hipGetErrorString(D.last_error));
-        return st;
-    };
-    BatchHost H;
-    std::vector<std::pair<uint32_t, uint32_t>> pairs;
-    std::vector<int32_t> text_of_view;
-    std::vector<uint64_t> base_of_view;
-    uint32_t max_m = 1;
+// Picks the members of the next step (admitting pending requests first) and
+// lays out its work list. Returns false when there is nothing to search (after
+// waiting for work when `may_wait`, i.e. no step is in flight) or on stop.
+bool hc_server::build(Step &S, std::vector<std::shared_ptr<Request>> &uploads, bool may_wait) {
+    S.members.clear();
+    S.base.clear();
+    S.wraps.clear();
+    uploads.clear();
     {
-        std::vector<int32_t> view_of_text(texts.size(), -1);
-        H.pats.assign(slots, BPat{});
-        for (auto &r : members) {
-            int32_t &v = view_of_text[r->text];
-            if (v < 0) {
-                const Text &t = texts[r->text];
-                v = int32_t(H.views.size());
-                const uint64_t base = t.cursor * kServeChunk;
-                H.views.push_back(TextView{t.d + base, t.n - base, std::min<uint64_t>(kServeChunk, t.n - base)});
-                text_of_view.push_back(r->text);
-                base_of_view.push_back(base);
-            }
-            H.pats[r->slot] = r->bp;
-            pairs.push_back({uint32_t(r->slot), uint32_t(v)});
-            max_m = std::max<uint32_t>(max_m, r->bp.m);
+        std::unique_lock<std::mutex> g(mu);
+        for (;;) {
+            if (stop) return false;
+            admit(uploads);
+            for (auto &r : active)
+                if (r && r->to_issue > 0) S.members.push_back(r);
+            if (!S.members.empty()) break;
+            cv_done.notify_all();   // immediate completions
+            if (!may_wait) return false;
+            cv_work.wait(g);
         }
-        // a view needs the halo of its longest pattern only
-        std::vector<uint32_t> span(H.views.size(), 1);
-        for (auto &r : members) {
-            const int32_t v = view_of_text[r->text];
-            span[v] = std::max<uint32_t>(span[v], r->bp.m);
-        }
-        for (size_t v = 0; v < H.views.size(); ++v)
-            H.views[v].len = std::min<uint64_t>(H.views[v].len, H.views[v].start_limit + span[v] - 1);
     }
-    // geometry for the longest active pattern, rounded up to limit re-tuning
+    // the scheduler alone changes the fields below
+    BatchHost &H = S.H;
+    H.views.clear();
+    H.pats.assign(slots, BPat{});
+    std::vector<int32_t> view_of_text(texts.size(), -1);
+    std::vector<uint32_t> span;
+    std::vector<std::pair<uint32_t, uint32_t>> pairs;
+    uint32_t max_m = 1;
+    S.bytes = 0;
+    for (auto &r : S.members) {
+        int32_t &v = view_of_text[r->text];
+        const Text &t = texts[r->text];
+        if (v < 0) {
+            v = int32_t(H.views.size());
+            const uint64_t base = t.cursor * kServeChunk;
+            H.views.push_back(TextView{t.d + base, t.n - base, std::min<uint64_t>(kServeChunk, t.n - base)});
+            span.push_back(1);
+        }
+        span[v] = std::max<uint32_t>(span[v], r->bp.m);
+        H.pats[r->slot] = r->bp;
+        pairs.push_back({uint32_t(r->slot), uint32_t(v)});
+        max_m = std::max<uint32_t>(max_m, r->bp.m);
+        S.base.push_back(t.cursor * kServeChunk);
+        S.wraps.push_back(uint8_t(t.cursor == 0 && r->started));
+        r->started = true;
+        --r->to_issue;
+        S.bytes += H.views[v].start_limit;
+    }
+    // a view needs the halo of its longest pattern only
+    for (size_t v = 0; v < H.views.size(); ++v)
+        H.views[v].len = std::min<uint64_t>(H.views[v].len, H.views[v].start_limit + span[v] - 1);
+    // every text of this step moves on by one chunk
+    for (size_t t = 0; t < texts.size(); ++t)
+        if (view_of_text[t] >= 0) texts[t].cursor = (texts[t].cursor + 1) % texts[t].chunks;
+    // geometry for the longest pattern, rounded up to limit re-tuning
     uint32_t bucket = 64;
     while (bucket < max_m) bucket *= 2;
-    if (bucket != D.max_m || D.tile == 0) {
-        hc_status st = batch_geometry(D, std::min<uint32_t>(bucket, uint32_t(kMaxM)), table_bytes, uint32_t(w));
-        if (st != HC_OK) return fail("geometry", st);
+    bucket = std::min<uint32_t>(bucket, uint32_t(kMaxM));
+    if (bucket != S.D.max_m || S.D.tile == 0) {
+        if (batch_geometry(S.D, bucket, table_bytes, uint32_t(w)) != HC_OK) S.D.tile = 0;
     }
-    batch_build(H, pairs, D.tile, kBatchGroup);
-    hc_status st = batch_upload(H, D, stream);
-    if (st != HC_OK) return fail("upload", st);
-    const size_t np = pairs.size();
-    if (d_off.ensure((np + 1) * 8) != HC_OK || pinned(h_off, h_off_cap, np + 1) != HC_OK)
-        return fail("offsets", HC_ENOMEM);
-    int64_t cap = int64_t(np * kResultReserve);
-    if (d_pos.bytes / 8 > size_t(cap)) cap = int64_t(d_pos.bytes / 8);
-    if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
-    // a second run, with room for everything the first one counted, fits;
-    // two more runs are allowed before the step fails
-    unsigned long long reserved_first = 0;
-    for (int attempt = 0; attempt < 4; ++attempt) {
-        if ((st = batch_enqueue(D, d_pos.as<int64_t>(), cap, d_off.as<int64_t>(), stream)) != HC_OK)
-            return fail("launch", st);
-        if (hipMemcpyAsync(h_ctl, D.ctl.p, 4 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipMemcpyAsync(h_off, d_off.p, (np + 1) * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess)
-            return fail("counts", HC_EHIP);
-        const uint64_t total = uint64_t(h_off[np]);
-        const bool short_scratch = h_ctl[2] != 0ull, short_out = total > uint64_t(cap);
-        if (short_scratch && batch_grow_scratch(D, h_ctl[1], total) != HC_OK) return fail("scratch", HC_ENOMEM);
+    if (S.D.tile) batch_build(H, pairs, S.D.tile, kBatchGroup);
+    return true;
+}
+
+// Stages the tables of newly admitted requests and enqueues the step: the
+// scatter of the new tables, the batched search, and the read-back of the
+// control words and the per-pair offsets, then records S.counted.
+hc_status hc_server::enqueue(Step &S, const std::vector<std::shared_ptr<Request>> &uploads) {
+    if (S.D.tile == 0) return HC_EINVAL;
+    if (!uploads.empty()) {
+        const size_t entry = size_t(table_bytes) + kXStride + sizeof(BPat), need = entry * uploads.size();
+        if (S.h_up.ensure(need) != HC_OK || S.h_up_slots.ensure(uploads.size()) != HC_OK ||
+            S.d_up.ensure(need) != HC_OK || S.d_up_slots.ensure(uploads.size() * 4) != HC_OK)
+            return HC_ENOMEM;
+        for (size_t i = 0; i < uploads.size(); ++i) {
+            uint8_t *e = S.h_up.p + i * entry;
+            std::memcpy(e, uploads[i]->F.data(), table_bytes);
+            std::memset(e + table_bytes, 0, kXStride);
+            std::memcpy(e + table_bytes, uploads[i]->x.data(), uploads[i]->x.size());
+            std::memcpy(e + table_bytes + kXStride, &uploads[i]->bp, sizeof(BPat));
+            S.h_up_slots.p[i] = uint32_t(uploads[i]->slot);
+        }
+        if (hipMemcpyAsync(S.d_up.p, S.h_up.p, need, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(S.d_up_slots.p, S.h_up_slots.p, uploads.size() * 4, hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return HC_EHIP;
+        hc_status st = scatter_patterns(S.d_up.as<uint8_t>(), S.d_up_slots.as<uint32_t>(), uint32_t(uploads.size()),
+                                        table_bytes, kXStride, Fpool.as<uint8_t>(), xpool.as<uint8_t>(),
+                                        patpool.as<BPat>(), stream);
+        if (st != HC_OK) return st;
+    }
+    S.D.Fs = Fpool.as<uint8_t>();   // pattern index = slot
+    S.D.xs = xpool.as<uint8_t>();
+    S.D.Fs_bytes = Fpool.bytes;
+    S.D.xs_bytes = xpool.bytes;
+    S.D.pats_dev = patpool.as<BPat>();
+    hc_status st = batch_upload(S.H, S.D, stream);
+    if (st != HC_OK) return st;
+    const size_t np = S.members.size();
+    if (S.d_off.ensure((np + 1) * 8) != HC_OK || S.h_off.ensure(np + 1) != HC_OK || S.h_ctl.ensure(4) != HC_OK)
+        return HC_ENOMEM;
+    S.cap = std::max<int64_t>(int64_t(np * kResultReserve), int64_t(S.d_pos.bytes / 8));
+    if (S.d_pos.ensure(size_t(S.cap) * 8) != HC_OK) return HC_ENOMEM;
+    if ((st = batch_enqueue(S.D, S.d_pos.as<int64_t>(), S.cap, S.d_off.as<int64_t>(), stream)) != HC_OK) return st;
+    if (hipMemcpyAsync(S.h_ctl.p, S.D.ctl.p, 4 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(S.h_off.p, S.d_off.p, (np + 1) * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipEventRecord(S.counted, stream) != hipSuccess)
+        return HC_EHIP;
+    return HC_OK;
+}
+
+// Waits for a step's counts, runs it again if its scratch or output was too
+// small (once: the second run has room for everything the first counted),
+// and copies its positions to the host on the copy stream.
+hc_status hc_server::collect(Step &S) {
+    if (hipEventSynchronize(S.counted) != hipSuccess) return HC_EHIP;
+    const size_t np = S.members.size();
+    for (int attempt = 0;; ++attempt) {
+        const uint64_t total = uint64_t(S.h_off.p[np]);
+        const bool short_scratch = S.h_ctl.p[2] != 0ull, short_out = total > uint64_t(S.cap);
+        if (!short_scratch && !short_out) break;
+        if (attempt == 1) return HC_EHIP;   // cannot happen (see batch_grow_scratch)
+        if (short_scratch && batch_grow_scratch(S.D, S.h_ctl.p[1], total) != HC_OK) return HC_ENOMEM;
         if (short_out) {
-            cap = int64_t(total);
-            if (d_pos.ensure(size_t(cap) * 8) != HC_OK) return fail("positions", HC_ENOMEM);
+            // growing may free the old buffer: nothing of this step is in
+            // flight any more (its counts arrived)
+            S.cap = int64_t(total);
+            if (S.d_pos.ensure(size_t(S.cap) * 8) != HC_OK) return HC_ENOMEM;
         }
-        if (short_scratch || short_out) {
-            if (attempt >= 1)
-                std::fprintf(stderr,
-                             "hc_serve: second run short (scratch %d, out %d, total %llu, cap %lld, reserved %llu "
-                             "then %llu, scratch %llu, grid %u, items %u, entries %llu)\n",
-                             int(short_scratch), int(short_out), (unsigned long long)total, (long long)cap,
-                             reserved_first, h_ctl[1], (unsigned long long)D.scratch_cap, D.grid, D.n_items,
-                             (unsigned long long)D.n_entries);
-            reserved_first = h_ctl[1];
-            continue;
-        }
-        if (pinned(h_pos, h_pos_cap, total) != HC_OK) return fail("host positions", HC_ENOMEM);
-        if (total && (hipMemcpyAsync(h_pos, d_pos.p, total * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-                      hipStreamSynchronize(stream) != hipSuccess))
-            return fail("positions copy", HC_EHIP);
-        std::vector<int32_t> view_of_text(texts.size(), -1);
-        for (size_t v = 0; v < text_of_view.size(); ++v) view_of_text[text_of_view[v]] = int32_t(v);
-        bytes = 0;
-        for (size_t k = 0; k < np; ++k) {
-            Request &r = *members[k];
-            const int32_t v = view_of_text[r.text];
-            const int64_t base = int64_t(base_of_view[v]);
-            for (int64_t i = h_off[k]; i < h_off[k + 1]; ++i) r.pos.push_back(h_pos[i] + base);
-            bytes += H.views[v].start_limit;
-        }
-        return HC_OK;
+        hc_status st = short_scratch
+                           ? batch_enqueue(S.D, S.d_pos.as<int64_t>(), S.cap, S.d_off.as<int64_t>(), stream)
+                           : batch_emit(S.D, S.d_pos.as<int64_t>(), S.cap, S.d_off.as<int64_t>(), stream);
+        if (st != HC_OK) return st;
+        if (hipMemcpyAsync(S.h_ctl.p, S.D.ctl.p, 4 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipMemcpyAsync(S.h_off.p, S.d_off.p, (np + 1) * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipEventRecord(S.counted, stream) != hipSuccess || hipEventSynchronize(S.counted) != hipSuccess)
+            return HC_EHIP;
     }
-    return fail("retry", HC_EHIP);
+    const uint64_t total = uint64_t(S.h_off.p[np]);
+    if (S.h_pos.ensure(total) != HC_OK) return HC_ENOMEM;
+    if (total) {
+        if (hipStreamWaitEvent(copy_stream, S.counted, 0) != hipSuccess ||
+            hipMemcpyAsync(S.h_pos.p, S.d_pos.p, total * 8, hipMemcpyDeviceToHost, copy_stream) != hipSuccess ||
+            hipEventRecord(S.copied, copy_stream) != hipSuccess || hipEventSynchronize(S.copied) != hipSuccess)
+            return HC_EHIP;
+    }
+    return HC_OK;
+}
+
+// Hands a collected step's positions to its requests (in step order) and
+// completes the requests whose last chunk this was.
+void hc_server::finish(Step &S, hc_status st) {
+    const size_t np = S.members.size();
+    const auto now = Clock::now();
+    std::lock_guard<std::mutex> g(mu);
+    if (st == HC_OK) bytes_searched += double(S.bytes);
+    for (size_t k = 0; k < np; ++k) {
+        Request &r = *S.members[k];
+        if (r.done) continue;   // failed by an earlier step
+        if (st != HC_OK) {
+            r.status = st;
+            r.to_issue = 0;
+            r.to_take = 0;
+        } else {
+            if (S.wraps[k] && !r.wrapped) {
+                r.wrapped = true;
+                r.wrap_at = r.pos.size();
+            }
+            const int64_t base = int64_t(S.base[k]);
+            for (int64_t i = S.h_off.p[k]; i < S.h_off.p[k + 1]; ++i) r.pos.push_back(S.h_pos.p[i] + base);
+            --r.to_take;
+        }
+        if (r.to_take == 0) {
+            if (r.wrapped) std::rotate(r.pos.begin(), r.pos.begin() + ptrdiff_t(r.wrap_at), r.pos.end());
+            complete(r, now);
+            active[r.slot] = nullptr;
+            used_bytes -= per_request;
+        }
+    }
+    if (st != HC_OK) fatal = st;
+    cv_done.notify_all();
 }
 
 void hc_server::run() {
@@ -309,64 +397,48 @@ void hc_server::run() {
         cv_done.notify_all();
         return;
     }
+    std::deque<Step *> flight;   // enqueued, results not taken yet (step order)
+    std::vector<Step *> idle;
+    for (Step &S : steps) idle.push_back(&S);
+    std::vector<std::shared_ptr<Request>> uploads;
+    Clock::time_point busy_since;
     for (;;) {
-        std::vector<std::shared_ptr<Request>> uploads, members;
+        bool stopping = false;
         {
-            std::unique_lock<std::mutex> g(mu);
-            for (;;) {
-                if (stop) return;
-                admit(uploads);
-                bool any = !uploads.empty();
-                for (auto &r : active)
-                    if (r) any = true;
-                if (any) break;
-                cv_done.notify_all();   // immediate completions
-                cv_work.wait(g);
-            }
-            for (auto &r : active)
-                if (r) members.push_back(r);
+            std::lock_guard<std::mutex> g(mu);
+            stopping = stop;
         }
-        const auto t0 = Clock::now();
-        hc_status st = HC_OK;
-        if (!uploads.empty()) st = upload(uploads);
-        uint64_t bytes = 0;
-        if (st == HC_OK) st = step(members, bytes);
-        const double dt = std::chrono::duration<double>(Clock::now() - t0).count();
-        std::lock_guard<std::mutex> g(mu);
-        busy_s += dt;
-        bytes_searched += double(bytes);
-        std::vector<bool> moved(texts.size(), false);
-        for (auto &r : members) {
-            Text &t = texts[r->text];
-            if (!moved[r->text]) {
-                moved[r->text] = true;
-                t.cursor = (t.cursor + 1) % t.chunks;
+        if (stopping) break;
+        // keep kSteps steps in flight while there is work
+        if (!idle.empty()) {
+            Step &S = *idle.back();
+            if (build(S, uploads, flight.empty())) {
+                const hc_status st = enqueue(S, uploads);
+                if (flight.empty()) busy_since = Clock::now();
+                idle.pop_back();
+                if (st != HC_OK) {
+                    // a failed enqueue leaves nothing of this step to wait for
+                    (void)hipStreamSynchronize(stream);
+                    finish(S, st);
+                    idle.push_back(&S);
+                } else {
+                    flight.push_back(&S);
+                }
+                continue;
             }
+            if (flight.empty()) continue;   // woken without work, or stopping
         }
-        const auto now = Clock::now();
-        for (auto &r : members) {
-            const Text &t = texts[r->text];
-            if (st != HC_OK) {
-                r->status = st;
-                r->chunks_left = 1;
-            }
-            if (!r->wrapped && t.cursor == 0 && r->chunks_left > 1) {
-                r->wrapped = true;
-                r->wrap_at = r->pos.size();
-            }
-            if (--r->chunks_left == 0) {
-                if (r->wrapped)
-                    std::rotate(r->pos.begin(), r->pos.begin() + ptrdiff_t(r->wrap_at), r->pos.end());
-                r->done = true;
-                done_q.push_back(r->id);
-                active[r->slot] = nullptr;
-                used_bytes -= per_request;
-                lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
-            }
+        Step &S = *flight.front();
+        flight.pop_front();
+        finish(S, collect(S));
+        idle.push_back(&S);
+        if (flight.empty()) {
+            std::lock_guard<std::mutex> g(mu);
+            busy_s += std::chrono::duration<double>(Clock::now() - busy_since).count();
         }
-        if (st != HC_OK) fatal = st;
-        cv_done.notify_all();
     }
+    (void)hipStreamSynchronize(stream);
+    (void)hipStreamSynchronize(copy_stream);
 }
 
 extern "C" {
@@ -401,16 +473,19 @@ hc_status hc_serve_create(const uint8_t *const *d_texts, const int64_t *n, int32
     S->slots = uint32_t(std::min<uint64_t>(kMaxSlots, S->budget / S->per_request));
     S->active.assign(S->slots, nullptr);
     if (S->Fpool.ensure(size_t(S->slots) * S->table_bytes) != HC_OK ||
-        S->xpool.ensure(size_t(S->slots) * kXStride + 64) != HC_OK)
+        S->xpool.ensure(size_t(S->slots) * kXStride + 64) != HC_OK ||
+        S->patpool.ensure(size_t(S->slots) * sizeof(BPat)) != HC_OK)
         return HC_ENOMEM;
-    if (hipMemset(S->xpool.p, 0, S->xpool.bytes) != hipSuccess) return HC_EHIP;
-    S->D.Fs = S->Fpool.as<uint8_t>();   // pattern index = slot
-    S->D.xs = S->xpool.as<uint8_t>();
-    S->D.Fs_bytes = S->Fpool.bytes;
-    S->D.xs_bytes = S->xpool.bytes;
-    if (hipHostMalloc(reinterpret_cast<void **>(&S->h_ctl), 64, hipHostMallocDefault) != hipSuccess)
-        return HC_ENOMEM;
-    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) return HC_EHIP;
+    if (hipMemset(S->xpool.p, 0, S->xpool.bytes) != hipSuccess ||
+        hipMemset(S->patpool.p, 0, S->patpool.bytes) != hipSuccess)
+        return HC_EHIP;
+    for (Step &x : S->steps)
+        if (hipEventCreateWithFlags(&x.counted, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&x.copied, hipEventDisableTiming) != hipSuccess)
+            return HC_EHIP;
+    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) != hipSuccess)
+        return HC_EHIP;
     // the texts were written on other streams: make them visible to ours
     if (hipDeviceSynchronize() != hipSuccess) return HC_EHIP;
     hc_server *raw = S.get();

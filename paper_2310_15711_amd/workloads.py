@@ -274,6 +274,7 @@ def request_stream(texts: Sequence[np.ndarray], rate: float, duration: float,
     """Open-loop Poisson arrivals at ``rate`` per second for ``duration`` s."""
     g = rng(cfg, 2, sub)
     out: List[Request] = []
+    alphabets = {}   # symbols of each text's first 64 KiB, computed once per text
     t = 0.0
     while True:
         t += float(g.exponential(1.0 / rate))
@@ -288,7 +289,9 @@ def request_stream(texts: Sequence[np.ndarray], rate: float, duration: float,
             x = y[off:off + m].tobytes()
         else:
             off = -1
-            alphabet = np.unique(y[: min(int(y.size), 1 << 16)])
+            if ti not in alphabets:
+                alphabets[ti] = np.unique(y[: min(int(y.size), 1 << 16)])
+            alphabet = alphabets[ti]
             x = alphabet[g.integers(0, alphabet.size, size=m)].astype(np.uint8).tobytes()
         out.append(Request(arrival=t, text=ti, pattern=x, extracted_at=off))
     return out
