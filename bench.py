@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="single workload: leave out the batched and served summaries")
     ap.add_argument("--serve-rates", default="1000,3000,10000,30000,100000")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-threads", type=int, default=4, help="native submitter threads")
     ap.add_argument("--serve-text-mib", type=int, default=128)
     ap.add_argument("--serve-budget-mib", type=int, default=2048)
     ap.add_argument("--serve-check", type=int, default=1000,
@@ -51,6 +52,10 @@ def parse():
     ap.add_argument("--batch-texts", type=int, default=64)
     ap.add_argument("--batch-patterns", type=int, default=4096)
     ap.add_argument("--batch-params", default=None, help="q,alpha,w for the batch plan (0 = library choice)")
+    ap.add_argument("--batch-oracle-pairs", type=int, default=1000,
+                    help="batched workload: seeded pairs compared with the oracle")
+    ap.add_argument("--serve-oracle", type=int, default=1000,
+                    help="served requests (over all rates) compared with the oracle")
     ap.add_argument("--no-per-pattern", action="store_true",
                     help="batched workload: skip the per-pattern launch baseline")
     ap.add_argument("--per-length", type=int, default=100, help="patterns per (sigma, m)")
@@ -76,6 +81,7 @@ def parse():
                     help="oracle sample: patterns per (sigma, m)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--detail", action="store_true", help="print per-(sigma, m) figures to stderr")
+    ap.add_argument("--write-cells", default=None, help="write the per-(sigma, m) markdown table here")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--summarize", nargs=4, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "CALIB_PREFIX"),
@@ -238,6 +244,77 @@ def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
     print(json.dumps(tj))
 
 
+def method_read_fractions(pats, infos):
+    """Per launch: the share of the text's 128-byte lines the method reads
+    (1 for m <= 32; else from profiles/hc_method_bytes.json; None when the
+    table has no entry for that sigma, m, q, alpha, w)."""
+    path = os.path.join(ROOT, "profiles", "hc_method_bytes.json")
+    table = json.load(open(path))["read_fraction"] if os.path.exists(path) else {}
+    out = []
+    for (s, m, _, _), inf in zip(pats, infos):
+        if m <= 32:
+            out.append(1.0)
+            continue
+        out.append(table.get(str(s), {}).get(str(m), {}).get(f"{inf['q']},{inf['alpha']},{inf['w']}"))
+    return out
+
+
+def write_cells(args, cells, pats, launch_ms, texts, cnt, infos, read_frac, launches, workload):
+    """Markdown table per (sigma, m): median call time, text GB/s, the
+    method's read share and method GB/s (HIP events around each call)."""
+    lines = [f"# Single-pattern search per cell: {workload}", "",
+             "Per (sigma, m): the launch tuple used, median call time (search + emit kernels, HIP events "
+             "on the launch stream, mean over steps per pattern, median over patterns), text GB/s = n / "
+             "time, the share of 128-byte text lines the sequential searching phase reads with the same "
+             "(q, alpha, w) (`hc_method_bytes.json`; 1 for m <= 32), and method GB/s = (that share x n + "
+             "8 x occurrences + table + m) / time.", "",
+             "Command: `" + " ".join(sys.argv) + "`", "",
+             "| sigma | m | q, alpha, w | segment, schedule, variant | median us | text GB/s | read share | "
+             "method GB/s |", "|---|---|---|---|---|---|---|---|"]
+    for (s, m), idx in sorted(cells.items()):
+        us = float(np.median([launch_ms[i] for i in idx])) * 1e3
+        n = texts[s].size
+        inf = infos[idx[0]]
+        fr = read_frac[idx[0]]
+        occ = float(np.median([int(cnt[i]) for i in idx]))
+        mb = (fr * n + 8 * occ + inf["F"].size * inf["w"] // 8 + m) if fr is not None else None
+        lc = launches[idx[0]]
+        lines.append(f"| {s} | {m} | {inf['q']}, {inf['alpha']}, {inf['w']} | {lc[0]}, {lc[1]}, {lc[2]} | "
+                     f"{us:.2f} | {n / us / 1e3:.1f} | {fr if fr is not None else '-'} | "
+                     f"{(mb / us / 1e3) if mb is not None else float('nan'):.1f} |")
+    with open(args.write_cells, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def check_single(pats, sample, wants, cnt, handles, launches, dtexts, stream):
+    """Oracle parity of the timed single-pattern launches: for each sampled
+    pattern, the count its timed launch reported, and the complete list of a
+    re-run with the same (q, alpha, w) and launch shape into a buffer of its
+    own, compared element by element with the oracle's list."""
+    import torch
+
+    from paper_2310_15711_amd import binding as B
+
+    dev = torch.device("cuda:0")
+    equal, bad = 0, []
+    for i, want in zip(sample, wants):
+        s = pats[i][0]
+        buf = torch.empty(int(want.size) + 16, dtype=torch.int64, device=dev)
+        c1 = torch.zeros(1, dtype=torch.int64, device=dev)
+        B.hc_search_async(handles[i], dtexts[s], buf, c1, launch=launches[i], stream=stream)
+        torch.cuda.synchronize()
+        c = int(c1.item())
+        ok = int(cnt[i]) == want.size and c == want.size and \
+            np.array_equal(buf[:min(c, want.size)].cpu().numpy(), want)
+        equal += int(ok)
+        if not ok and len(bad) < 5:
+            bad.append({"sigma": s, "m": pats[i][1], "offset": int(pats[i][2]), "timed_count": int(cnt[i]),
+                        "rerun_count": c, "oracle_count": int(want.size)})
+    return {"checked": len(sample), "equal": equal, "exact": equal == len(sample),
+            "what": "sampled patterns: timed launch's count and a re-run's complete list (same tuned "
+                    "launch) vs the oracle's brute force", "mismatches": bad}
+
+
 def run_batched(args):
     """Batched workload: texts with log-normal lengths in [64 KiB, 16 MiB] over
     4, 20 or 64 symbols, patterns with log-uniform lengths in [4, 1024], every
@@ -282,6 +359,25 @@ def run_batched(args):
         times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
     value = pair_bytes / (ms * 1e-3) / 1e9
+    # oracle parity: a seeded sample of pairs, complete lists
+    from oracle import hc_oracle as O
+
+    po_h = pair_off.cpu().numpy()
+    g = np.random.default_rng([231015711, 4, 9, 0])
+    sample = np.sort(g.choice(len(pp), size=min(len(pp), args.batch_oracle_pairs), replace=False))
+    t1 = time.time()
+    equal, bad = 0, []
+    for k in sample:
+        want = O.occurrences(b.patterns[int(pp[k])], b.texts[int(pt[k])])
+        lo, hi = int(po_h[k]), int(po_h[k + 1])
+        ok = hi - lo == want.size and np.array_equal(pos[lo:hi].cpu().numpy(), want)
+        equal += int(ok)
+        if not ok and len(bad) < 5:
+            bad.append({"pair": int(k), "count": hi - lo, "oracle_count": int(want.size)})
+    parity = {"checked": int(sample.size), "equal": equal, "exact": equal == int(sample.size),
+              "what": "seeded sample of (pattern, text) pairs of the timed plan, complete lists vs the "
+                      "oracle's brute force", "mismatches": bad}
+    log(f"batched oracle parity in {time.time() - t1:.1f}s: {equal}/{sample.size}")
     per_pattern = None
     if not args.no_per_pattern:
         handles = [B.hc_preprocess(x) for x in b.patterns]
@@ -319,6 +415,7 @@ def run_batched(args):
                                f"(m log-uniform 4..1024), {len(pp)} pairs, one plan run per step",
                    "pattern_x_text_bytes": pair_bytes, "occurrences": int(total),
                    "plan_create_s": round(plan_s, 2)},
+        "parity": parity,
         "per_pattern_launches": per_pattern,
         "speedup_vs_per_pattern_gpu_busy": (round(value / per_pattern["gbps_gpu_busy"], 2)
                                             if per_pattern else None),
@@ -332,11 +429,14 @@ def run_served(args):
     """Served workload: eight resident 128 MiB texts (four iid bytes, four
     order-2 Markov walks), open-loop Poisson arrivals at each rate, every
     request a text and a pattern of log-uniform length in [4, 2048]
-    (extracted with probability 1/2). Latency = observed completion minus
-    scheduled arrival (p50/p99 after the first 10% of arrivals); aggregate
-    GB/s = text bytes of all requests over first arrival to last completion.
-    A seeded sample of requests per rate is compared with hc_search alone."""
-    import threading
+    (extracted with probability 1/2). Arrivals are submitted by native
+    threads at their scheduled times (libhc_loadgen), completions taken by a
+    native collector. Latency = observed completion minus scheduled arrival
+    (p50/p99 after the first 10% of arrivals); aggregate GB/s = text bytes of
+    all requests over first arrival to last completion. A seeded sample of
+    requests per rate is compared with hc_search alone, and a smaller one
+    with the oracle's brute force."""
+    import ctypes
 
     import torch
 
@@ -349,74 +449,88 @@ def run_served(args):
     dtexts = [torch.from_numpy(t).to(dev) for t in texts]
     torch.cuda.synchronize()
     log(f"served inputs in {time.time() - t0:.1f}s: {len(texts)} texts x {args.serve_text_mib} MiB")
+    B.lib()
+    gen = ctypes.CDLL(os.path.join(ROOT, "paper_2310_15711_amd", "libhc_loadgen.so"))
+    P = ctypes.c_void_p
+    gen.hc_loadgen_run.restype = ctypes.c_int
+    gen.hc_loadgen_run.argtypes = [P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int32, ctypes.c_double,
+                                   P, P, P, P, ctypes.c_int64, P]
     rates = [float(r) for r in args.serve_rates.split(",")]
     out = {}
+    from oracle import hc_oracle as O
+
+    o_checked, o_equal, o_bad = 0, 0, []
+    start_delay = 0.05
     for ri, rate in enumerate(rates):
         reqs = W.request_stream(texts, rate, args.serve_seconds, sub=ri)
-        srv = B.Server(dtexts, args.serve_budget_mib << 20)
         n = len(reqs)
-        ids = [0] * n
-        submit_t = np.zeros(n)
-        done_t = {}
-        results = {}
-        t_start = time.perf_counter() + 0.05
-
-        def submitter():
-            for i, r in enumerate(reqs):
-                ahead = t_start + r.arrival - time.perf_counter()
-                if ahead > 5e-4:
-                    time.sleep(ahead - 2e-4)
-                submit_t[i] = time.perf_counter()
-                ids[i] = srv.submit(r.text, r.pattern)
-
-        th = threading.Thread(target=submitter)
-        th.start()
-        want = set()
-        got = 0
-        idx_of = {}
-        deadline = time.perf_counter() + 600
-        while got < n:
-            rid = srv.next_done(timeout_us=20_000)
-            if rid is None:
-                if time.perf_counter() > deadline:
-                    raise RuntimeError("served requests did not complete")
-                continue
-            tdone = time.perf_counter()
-            st, pos, cnt = srv.poll(rid, cap=1 << 22)
-            if st != B.HC_OK:
-                st, pos, cnt = srv.poll(rid, cap=cnt)
-            done_t[rid] = tdone
-            results[rid] = pos
-            got += 1
-        th.join()
-        sstats = srv.stats()
-        srv.close()
-        arrival = np.array([t_start + r.arrival for r in reqs])
-        done = np.array([done_t[ids[i]] for i in range(n)])
-        lat = (done - arrival) * 1e3
-        keep = np.argsort(arrival)[n // 10:]
-        text_bytes = float(sum(texts[r.text].size for r in reqs))
-        makespan = float(done.max() - arrival.min())
-        # exact results: a seeded sample against hc_search alone
+        arrival = np.array([r.arrival for r in reqs], dtype=np.float64) + start_delay
+        tid = np.array([r.text for r in reqs], dtype=np.int32)
+        pat = np.frombuffer(b"".join(r.pattern for r in reqs), dtype=np.uint8)
+        poff = np.zeros(n + 1, dtype=np.int64)
+        poff[1:] = np.cumsum([len(r.pattern) for r in reqs])
         g = np.random.default_rng([231015711, 5, 9, ri])
         sample = g.choice(n, size=min(n, args.serve_check), replace=False)
-        same = True
+        per_rate = -(-args.serve_oracle // len(rates))
+        osample = sample[:min(sample.size, per_rate)]
+        keep = np.zeros(n, dtype=np.uint8)
+        keep[sample] = 1
+        submit_s, done_s = np.zeros(n), np.zeros(n)
+        count = np.zeros(n, dtype=np.int64)
+        pos_cap = 1 << 25
+        pos = np.zeros(pos_cap, dtype=np.int64)
+        pos_off = np.zeros(n + 1, dtype=np.int64)
+        srv = B.Server(dtexts, args.serve_budget_mib << 20)
+        rc = gen.hc_loadgen_run(srv.handle, n, arrival.ctypes.data, tid.ctypes.data, pat.ctypes.data,
+                                poff.ctypes.data, keep.ctypes.data, args.serve_threads, 600.0,
+                                submit_s.ctypes.data, done_s.ctypes.data, count.ctypes.data, pos.ctypes.data,
+                                pos_cap, pos_off.ctypes.data)
+        if rc != B.HC_OK:
+            raise RuntimeError(f"served load failed: {B.strerror(rc)} ({rc})")
+        sstats = srv.stats()
+        srv.close()
+        lat = (done_s - arrival) * 1e3
+        keep_lat = np.argsort(arrival)[n // 10:]
+        text_bytes = float(sum(texts[r.text].size for r in reqs))
+        makespan = float(done_s.max() - arrival.min())
+
+        def result(i):
+            o = int(pos_off[i])
+            return None if o < 0 else pos[o:o + int(count[i])]
+
+        # exact results: the sample against hc_search alone, part of it
+        # against the oracle's brute force
+        same, checked_alone = True, 0
         for i in sample:
+            got = result(int(i))
+            if got is None:
+                continue
             r = reqs[int(i)]
             alone = B.find_all(B.hc_preprocess(r.pattern), dtexts[r.text]).cpu().numpy()
-            if not np.array_equal(alone, results[ids[int(i)]]):
+            checked_alone += 1
+            if not np.array_equal(alone, got):
                 same = False
                 break
+        for i in osample:
+            got = result(int(i))
+            r = reqs[int(i)]
+            want = O.occurrences(r.pattern, texts[r.text])
+            ok = got is not None and np.array_equal(want, got)
+            o_equal += int(ok)
+            o_checked += 1
+            if not ok and len(o_bad) < 5:
+                o_bad.append({"rate": rate, "request": int(i), "text": r.text, "m": len(r.pattern),
+                              "count": int(count[int(i)]), "oracle_count": int(want.size)})
         out[str(int(rate))] = {
             "requests": n, "offered_rate": rate,
-            "submitted_rate": round(n / float(submit_t.max() - submit_t.min() + 1e-9), 1),
-            "p50_ms": round(float(np.percentile(lat[keep], 50)), 3),
-            "p99_ms": round(float(np.percentile(lat[keep], 99)), 3),
+            "submitted_rate": round(n / float(submit_s.max() - submit_s.min() + 1e-9), 1),
+            "p50_ms": round(float(np.percentile(lat[keep_lat], 50)), 3),
+            "p99_ms": round(float(np.percentile(lat[keep_lat], 99)), 3),
             "agg_gbps": round(text_bytes / makespan / 1e9, 1),
             "server_busy_gbps": round(sstats["agg_gbps"], 1),
             "server_p50_ms": round(sstats["p50_us"] / 1e3, 3),
             "server_p99_ms": round(sstats["p99_us"] / 1e3, 3),
-            "checked_vs_alone": int(sample.size), "same_as_alone": same,
+            "checked_vs_alone": checked_alone, "same_as_alone": same,
         }
         log(f"served rate {rate:.0f}/s: {out[str(int(rate))]}")
     # baseline: the same kind of requests, one hc_search_async launch each,
@@ -449,6 +563,9 @@ def run_served(args):
                         f"(4 iid bytes, 4 order-2 Markov), Poisson arrivals for "
                         f"{args.serve_seconds} s per rate, m log-uniform 4..2048",
             "budget_mib": args.serve_budget_mib, "rates": out,
+            "parity": {"checked": o_checked, "equal": o_equal, "exact": o_equal == o_checked,
+                       "what": "seeded sample of served requests (spread over the rates), complete "
+                               "lists vs the oracle's brute force", "mismatches": o_bad},
             "per_request_launches": baseline,
             "speedup_vs_per_request_gpu_busy": round(best["agg_gbps"] / baseline["gbps_gpu_busy"], 2)}
 
@@ -603,14 +720,28 @@ def main():
     alg_bytes = np.array([texts[s].size + 8 * int(c) + inf["F"].size * inf["w"] // 8 + m
                           for (s, m, _, _), c, inf in zip(pats, cnt, infos)], dtype=np.float64)
     achieved = float(alg_bytes.mean() / (avg_launch_ms * 1e-3) / 1e9)
+    # the method's own bytes: the share of the text's 128-byte lines that the
+    # sequential searching phase reads with the same (q, alpha, w), from the
+    # table the oracle's scan wrote (every line for m <= 32)
+    read_frac = method_read_fractions(pats, infos)
+    method_bytes = None
+    if all(f is not None for f in read_frac):
+        method_bytes = np.array([texts[s].size * f + 8 * int(c) + inf["F"].size * inf["w"] // 8 + m
+                                 for (s, m, _, _), c, inf, f in zip(pats, cnt, infos, read_frac)],
+                                dtype=np.float64)
+    achieved_method = (float(method_bytes.mean() / (avg_launch_ms * 1e-3) / 1e9)
+                       if method_bytes is not None else None)
 
-    detail = {}
+    detail, cells = {}, {}
     for i, (s, m, _, _) in enumerate(pats):
         detail.setdefault(f"{s}/{m}", []).append(texts[s].size / (launch_ms[i] * 1e-3) / 1e9)
+        cells.setdefault((s, m), []).append(i)
     detail = {k: round(float(np.median(v)), 1) for k, v in detail.items()}
     if args.detail:
         for k, v in detail.items():
             log(f"  sigma/m {k:10s} median text GB/s {v:9.1f}")
+    if args.write_cells:
+        write_cells(args, cells, pats, launch_ms, texts, cnt, infos, read_frac, launches, workload)
 
     traffic = None
     if os.path.exists(args.traffic_json):
@@ -625,29 +756,38 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "hc_search_kernel + hc_emit_kernel (one search call)",
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2),
-                "alg_bytes_per_launch": round(float(alg_bytes.mean()))}
+                "alg_bytes_per_launch": round(float(alg_bytes.mean())),
+                "frac_text": round(achieved / HBM_PEAK_GBPS, 4),
+                "achieved_method": round(achieved_method, 1) if achieved_method else None,
+                "frac_method": round(achieved_method / HBM_PEAK_GBPS, 4) if achieved_method else None,
+                "method_bytes_per_launch": round(float(method_bytes.mean())) if method_bytes is not None else None,
+                "method_bytes_source": "profiles/hc_method_bytes.json (share of 128-byte text lines the "
+                                       "sequential searching phase reads, per sigma, m, q, alpha, w)"}
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
         from oracle import hc_oracle as O
 
         th = O.default_threads()
         sample = []
-        seen = set()
-        for (s, m, off, x) in pats:
-            key = (s, m)
-            if sum(1 for k in seen if k[:2] == key) < args.cpu_sample_patterns:
-                seen.add((s, m, off))
-                sample.append((s, m, x))
+        per_cell = {}
+        for i, (s, m, off, x) in enumerate(pats):
+            if per_cell.get((s, m), 0) < args.cpu_sample_patterns:
+                per_cell[(s, m)] = per_cell.get((s, m), 0) + 1
+                sample.append(i)
         t1 = time.perf_counter()
         nbytes = 0
-        for s, m, x in sample:
-            O.count(x, texts[s], threads=th)
+        wants = []
+        for i in sample:
+            s, m, _, x = pats[i]
+            wants.append(O.occurrences(x, texts[s], threads=th))
             nbytes += texts[s].size
         dt = time.perf_counter() - t1
         cpu = {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": th, "kind": "oracle",
                "sample": f"{len(sample)} patterns ({args.cpu_sample_patterns} per sigma and m), each "
                          f"over its full {args.text_mib} MiB text, {dt:.1f} s"}
+        parity = check_single(pats, sample, wants, cnt, handles, launches, dtexts, stream)
 
     rec = {
         "metric": "text GB/s per pattern (HC vs batched) + % HBM peak; p50/p99 search latency",
@@ -674,6 +814,7 @@ def main():
                                 if tuned else None)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parity": parity,
         "detail_median_text_gbps": detail,
     }
     if args.workload == "single" and not args.no_extras:
@@ -681,6 +822,7 @@ def main():
         torch.cuda.empty_cache()
         bt = run_batched(args)
         rec["batched"] = {"value": bt["value"], "unit": "GB/s", "config": bt["config"],
+                          "parity": bt["parity"],
                           "per_pattern_launches": bt["per_pattern_launches"],
                           "speedup_vs_per_pattern_gpu_busy": bt["speedup_vs_per_pattern_gpu_busy"]}
         rec["served"] = run_served(args)

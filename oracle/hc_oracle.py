@@ -22,6 +22,11 @@ its printed listings:
   words still empty after all links (Section 3.4, first optimisation).
 * ``chain_head_hash``: H_v, the hash of the first q-gram of the chain that
   ends at the last pattern position (Section 3.4, second optimisation).
+* ``hc_scan`` (C, ``hc_seq.c``): the same searching phase over a whole
+  text, reporting the occurrences it finds and how many distinct memory
+  lines of the text it reads -- the text bytes the method itself needs.
+  Pinned against the brute force (occurrences) and against
+  ``hc_search_sequential`` (lines read) in the tests.
 * ``hc_search_sequential``: the searching phase of Section 3.3 run one
   window at a time, for tiny inputs. It exists to pin ``link_table`` and
   ``chain_head_hash`` against brute force. It uses the verification reading
@@ -44,21 +49,22 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SOURCE_PATH = os.path.join(_HERE, "brute.c")
+SEQ_SOURCE_PATH = os.path.join(_HERE, "hc_seq.c")
 
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile brute.c into liboracle.so with gcc (plain C, -O2)."""
+    """Compile brute.c and hc_seq.c into liboracle.so with gcc (plain C, -O2)."""
     import subprocess
 
-    if force or not os.path.exists(LIB_PATH) or (
-        os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE_PATH)
+    if force or not os.path.exists(LIB_PATH) or any(
+        os.path.getmtime(LIB_PATH) < os.path.getmtime(src) for src in (SOURCE_PATH, SEQ_SOURCE_PATH)
     ):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-             SOURCE_PATH, "-o", tmp]
+             SOURCE_PATH, SEQ_SOURCE_PATH, "-o", tmp]
         )
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -77,6 +83,9 @@ def _load():
         lib.oracle_count.argtypes = [p, i64, p, i64, ctypes.c_int]
         lib.oracle_matches_at.restype = ctypes.c_int
         lib.oracle_matches_at.argtypes = [p, i64, p, i64, i64]
+        i32 = ctypes.c_int
+        lib.oracle_hc_scan.restype = i32
+        lib.oracle_hc_scan.argtypes = [p, i64, p, i64, i32, i32, i32, i64, i64, p, p, p]
         _lib = lib
     return _lib
 
@@ -227,8 +236,23 @@ def chain_head_hash(x: bytes, q: int, alpha: int) -> int:
 # Sequential searching phase (Section 3.3), tiny inputs only
 # ---------------------------------------------------------------------------
 
+def hc_scan(x, y, q: int, alpha: int, w: int, line: int = 128, max_hashes: int = 0):
+    """(occurrences, distinct line-byte blocks of y read, covered) of the
+    searching phase over y, by the C implementation in hc_seq.c. With
+    max_hashes > 0 the scan stops after hashing that many q-grams; every
+    window ending before `covered` was decided (covered = len(y) otherwise)."""
+    xa, ya = _as_u8(x), _as_u8(y)
+    occ, lines, cov = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = _load().oracle_hc_scan(xa.ctypes.data, int(xa.size), ya.ctypes.data if ya.size else None,
+                                int(ya.size), int(q), int(alpha), int(w), int(line), int(max_hashes),
+                                ctypes.byref(occ), ctypes.byref(lines), ctypes.byref(cov))
+    if rc != 0:
+        raise ValueError("oracle_hc_scan: bad arguments")
+    return occ.value, lines.value, cov.value
+
+
 def hc_search_sequential(x: bytes, y: bytes, q: int, alpha: int, w: int,
-                         table=None) -> List[int]:
+                         table=None, touched=None) -> List[int]:
     """Slide a window of length m; read q-grams backwards from its end.
 
     * The q-gram ending at the window end is hashed; an empty word means no
@@ -240,10 +264,18 @@ def hc_search_sequential(x: bytes, y: bytes, q: int, alpha: int, w: int,
     * When every q-gram in the window links, the window is a candidate: if the
       last hash read equals H_v and the window equals x, its start is
       reported; the window then advances by one position.
+
+    When ``touched`` is a set, the positions of y the search reads (every
+    hashed q-gram, every compared window) are added to it.
     """
     m, n = len(x), len(y)
     F, s, mask, Hv = link_table(x, q, alpha, w)
-    H = lambda e: qgram_hash(y[e - q + 1:e + 1], alpha, s)  # q-gram ending at e
+
+    def H(e):  # q-gram ending at e
+        if touched is not None:
+            touched.update(range(e - q + 1, e + 1))
+        return qgram_hash(y[e - q + 1:e + 1], alpha, s)
+
     out = []
     J = m - 1                          # window end
     while J < n:
@@ -263,8 +295,11 @@ def hc_search_sequential(x: bytes, y: bytes, q: int, alpha: int, w: int,
             z = F[v]
         if linked:
             start = J - m + 1
-            if v == Hv and y[start:start + m] == x:
-                out.append(start)
+            if v == Hv:
+                if touched is not None:
+                    touched.update(range(start, start + m))
+                if y[start:start + m] == x:
+                    out.append(start)
             J += 1
         else:
             J = e + m - q + 1

@@ -286,3 +286,110 @@ def test_sequential_hc_random():
         alpha = g.randint(1, 12)
         w = g.choice([8, 16, 32, 64])
         assert O.hc_search_sequential(x, y, q, alpha, w) == find_all(x, y)
+
+
+def _chain_order_table(x, q, alpha, w):
+    """F and H_v built in the order of the preprocessing figure of Section
+    3.2: chain by chain (the chain ending at m - i for i = min(m - q + 1, q)
+    down to 1), each walked from its last q-gram backwards, linking every
+    q-gram's word to the q-gram before it; H_v is the last hash the walks
+    compute; then the q-grams ending at q - 1 .. min(2q - 1, m) - 1 are marked
+    with 1 where their word is still empty. Hashes are read backwards from a
+    q-gram's end and reduced at every step (independent of the oracle's
+    start-to-end form reduced once)."""
+    m = len(x)
+    s, mask = alpha // q, (1 << alpha) - 1
+
+    def hash_ending_at(e):
+        v = 0
+        for k in range(q):
+            v = ((v << s) + x[e - k]) & mask
+        return v
+
+    F = [0] * (1 << alpha)
+    hv = None
+    for i in range(min(m - q + 1, q), 0, -1):
+        right = hash_ending_at(m - i)
+        e = m - i - q
+        while e >= q - 1:
+            left = hash_ending_at(e)
+            F[right] |= 1 << (left & (w - 1))
+            right = left
+            e -= q
+        hv = right
+    for e in range(q - 1, min(2 * q - 1, m)):
+        v = hash_ending_at(e)
+        if F[v] == 0:
+            F[v] = 1
+    return F, hv
+
+
+def test_link_table_equals_chain_order():
+    """The oracle's F (equation (1) over the pairs in index order, then the
+    marks) and H_v equal the chain-order construction, on random patterns
+    over small and large alphabets (repeated q-grams, bytes >= 0x80), every
+    q up to min(m, 8), tiny and usual alpha, every w."""
+    g = np.random.default_rng(3101)
+    for case in range(400):
+        m = int(g.integers(1, 70))
+        sigma = int(g.choice([2, 3, 4, 256]))
+        x = bytes((g.integers(0, sigma, size=m) * (255 // max(sigma - 1, 1))).astype(np.uint8))
+        q = int(g.integers(1, min(m, 8) + 1))
+        alpha = int(g.choice([1, 3, 8, 12]))
+        w = int(g.choice([8, 16, 32, 64]))
+        F, s, mask, hv = O.link_table(x, q, alpha, w)
+        F2, hv2 = _chain_order_table(x, q, alpha, w)
+        assert F == F2, (case, x.hex(), q, alpha, w)
+        assert hv == hv2, (case, x.hex(), q, alpha, w)
+
+
+def test_hc_scan_finds_the_brute_force_occurrences():
+    """The C sequential searching phase reports exactly as many occurrences
+    as the brute force, over random texts with planted copies, every q, tiny
+    and usual alpha, every w."""
+    g = np.random.default_rng(717)
+    for case in range(300):
+        sigma = int(g.choice([2, 4, 20, 256]))
+        n = int(g.integers(0, 20000))
+        m = int(g.integers(1, 80))
+        y = g.integers(0, sigma, size=n).astype(np.uint8)
+        if n >= m and g.random() < 0.7:
+            t = int(g.integers(0, n - m + 1))
+            x = y[t:t + m].tobytes()
+        else:
+            x = g.integers(0, sigma, size=m).astype(np.uint8).tobytes()
+        q = int(g.integers(1, min(m, 8) + 1))
+        alpha = int(g.choice([1, 4, 8, 12]))
+        w = int(g.choice([8, 16, 32, 64]))
+        occ, lines, cov = O.hc_scan(x, y, q, alpha, w)
+        assert occ == O.count(x, y), (case, n, m, q, alpha, w)
+        assert 0 <= lines <= n // 128 + 1 and cov == n
+        # stopped early: the windows decided so far are the brute force's
+        occ2, _, cov2 = O.hc_scan(x, y, q, alpha, w, max_hashes=50)
+        assert occ2 == (O.count(x, y[:cov2]) if cov2 >= m else 0), (case, cov2)
+
+
+def test_hc_scan_lines_equal_sequential_reads():
+    """The lines the C scan reads are those holding the positions the
+    Python sequential search reads (the same algorithm written separately),
+    at line sizes from 1 byte (every position read) to 128 bytes."""
+    g = np.random.default_rng(718)
+    for case in range(150):
+        sigma = int(g.choice([2, 4, 27]))
+        n = int(g.integers(0, 1500))
+        m = int(g.integers(1, 60))
+        y = g.integers(0, sigma, size=n).astype(np.uint8).tobytes()
+        if n >= m and g.random() < 0.6:
+            t = int(g.integers(0, n - m + 1))
+            x = y[t:t + m]
+        else:
+            x = g.integers(0, sigma, size=m).astype(np.uint8).tobytes()
+        q = int(g.integers(1, min(m, 8) + 1))
+        alpha = int(g.choice([2, 8, 12]))
+        w = int(g.choice([8, 32]))
+        touched = set()
+        occ = O.hc_search_sequential(x, y, q, alpha, w, touched=touched)
+        for line in (1, 4, 16, 128):
+            c_occ, c_lines, _ = O.hc_scan(x, y, q, alpha, w, line=line)
+            assert c_occ == len(occ)
+            assert c_lines == len({p // line for p in touched}), (case, line)
