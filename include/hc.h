@@ -210,6 +210,31 @@ hc_status hc_search_async(const hc_pattern *p, const uint8_t *d_y, int64_t n,
                           const hc_launch *launch, void *stream);
 
 /*
+ * hc_search_async_noalloc -- hc_search_async for callers that cannot
+ * allocate device memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation). Same arguments,
+ * results and stream ordering as hc_search_async, and the same two kernels;
+ * the per-tile results between them go to a fixed 64 MiB device array that
+ * the library holds on each device it runs on (until the process ends)
+ * instead of the per-stream workspace. The call allocates nothing:
+ *   - the pattern must already have its device copy on the current device
+ *     (made by any earlier hc_search / hc_search_async with it there), else
+ *     HC_EINVAL;
+ *   - a call whose per-tile results need more than 64 MiB gives HC_EINVAL
+ *     (they take 4 + 512 + tile/8 bytes per tile of `tile` window starts:
+ *     texts up to about 420 MiB at the default tile shapes);
+ *   - the first call on a device looks up the array's address and, like any
+ *     first launch of a kernel shape, fills host-side caches.
+ * Every call on one device shares the array: calls that overlap on that
+ * device (on different streams or from different threads without ordering)
+ * race and give wrong results; calls ordered on one stream are safe. Nothing
+ * in the array needs clearing between calls.
+ */
+hc_status hc_search_async_noalloc(const hc_pattern *p, const uint8_t *d_y, int64_t n,
+                                  int64_t *d_out, int64_t cap, int64_t *d_count,
+                                  const hc_launch *launch, void *stream);
+
+/*
  * Batched search: every listed (pattern, text) pair in one persistent launch
  * (one text tile is staged on chip once and searched for many patterns).
  *   d_text            device bytes holding all texts;

@@ -27,7 +27,7 @@ EXPORTED = (
     "hc_search_batched", "hc_batch_plan_create", "hc_batch_plan_run", "hc_batch_plan_free",
     "hc_serve_create", "hc_serve_submit", "hc_serve_poll", "hc_serve_next_done",
     "hc_serve_stats", "hc_serve_destroy", "hc_strerror", "hc_autotune", "hc_autotune_reset",
-    "hc_preprocess_many",
+    "hc_preprocess_many", "hc_search_async_noalloc",
 )
 
 
@@ -92,6 +92,7 @@ def lib():
         "hc_autotune": (i32, [p, i64, P(i64), i32, i32, p, p]),
         "hc_autotune_reset": (None, []),
         "hc_preprocess_many": (i32, [p, p, i32, p, p, i64, p, p, p]),
+        "hc_search_async_noalloc": (i32, [p, p, i64, p, i64, p, p, p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -220,6 +221,18 @@ def hc_search_async(p: Pattern, y, out, d_count, launch=None, stream=None, n=Non
                                _dev_ptr(d_count, "torch.int64"),
                                ctypes.byref(lc) if lc is not None else None, _stream_ptr(stream))
     return _check(st, "hc_search_async")
+
+
+def hc_search_async_noalloc(p: Pattern, y, out, d_count, launch=None, stream=None):
+    """hc_search_async without allocations (fixed device scratch); returns the
+    status (HC_EINVAL when the pattern is not resident on the device yet or
+    the text needs more scratch than the fixed array holds)."""
+    cap = int(out.numel()) if out is not None else 0
+    lc = _launch(launch)
+    return lib().hc_search_async_noalloc(p.handle, _dev_ptr(y, "torch.uint8") if y.numel() else None,
+                                         int(y.numel()), _dev_ptr(out, "torch.int64") if cap else None, cap,
+                                         _dev_ptr(d_count, "torch.int64"),
+                                         ctypes.byref(lc) if lc is not None else None, _stream_ptr(stream))
 
 
 def find_all(p: Pattern, y, cap: int = 1 << 16, stream=None):

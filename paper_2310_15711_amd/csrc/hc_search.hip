@@ -828,3 +828,63 @@ static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, c
 }
 
 }  // namespace hc
+
+// ----------------------------------------------------------------------------
+// hc_search_async_noalloc: the same two kernels with their per-tile results
+// in a fixed device array instead of the per-stream workspace.
+// ----------------------------------------------------------------------------
+
+namespace hc {
+
+// Bytes of the fixed array: per-tile results of texts up to about 420 MiB at
+// the default tile shapes ((4 + 4 * kSlot + tile / 8) bytes per tile).
+constexpr uint64_t kNoallocScratchBytes = uint64_t(64) << 20;
+
+// One copy per device, held until the process ends. Host code never passes
+// this name to a kernel: it stands for a host-side symbol, not the device
+// address; the address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current).
+static hc_status noalloc_scratch(void **out) {
+    static std::mutex mu;
+    static void *ptrs[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HC_EHIP;
+    std::lock_guard<std::mutex> g(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HC_EHIP;
+        ptrs[dev] = p;
+    }
+    *out = ptrs[dev];
+    return HC_OK;
+}
+
+}  // namespace hc
+
+extern "C" hc_status hc_search_async_noalloc(const hc_pattern *pc, const uint8_t *d_y, int64_t n,
+                                             int64_t *d_out, int64_t cap, int64_t *d_count,
+                                             const hc_launch *launch, void *stream) {
+    using namespace hc;
+    if (!pc || !d_count || n < 0 || cap < 0 || (cap > 0 && !d_out)) return HC_EINVAL;
+    if (n > 0 && !d_y) return HC_EINVAL;
+    if (n > int64_t(0xFFFFFFFFll)) return HC_EINVAL;
+    if (launch && (launch->segment < 0 || launch->segment > 4096 || launch->schedule < 0 ||
+                   launch->schedule > HC_SCHED_DENSE || launch->variant < 0 ||
+                   launch->variant > HC_VARIANT_SPARSE || launch->wg_per_cu < 0 || launch->wg_per_cu > 8))
+        return HC_EINVAL;
+    if (!device_info().ok) return HC_EHIP;
+    hc_pattern *p = const_cast<hc_pattern *>(pc);
+    const DeviceCopy *dc = pattern_resident(p);
+    if (!dc) return HC_EINVAL;   // not uploaded to this device yet (that would allocate)
+    void *fixed = nullptr;
+    const hc_status st = noalloc_scratch(&fixed);
+    if (st != HC_OK) return st;
+    const hc_launch lc = choose_launch(p->data, n, launch);
+    return launch_single(p, *dc, d_y, n, d_out, cap, d_count, lc, hipStream_t(stream), fixed,
+                         kNoallocScratchBytes);
+}
