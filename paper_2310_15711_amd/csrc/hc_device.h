@@ -437,6 +437,12 @@ __device__ __forceinline__ void stage_commit(const Stage<N> &st, uint8_t *lds_te
 // load, so nothing outside the text's pages is touched.
 // ----------------------------------------------------------------------------
 typedef const __attribute__((address_space(1))) uint32_t global_u32;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef u32x2 u32x2_a4 __attribute__((aligned(4)));
+typedef u32x3 u32x3_a4 __attribute__((aligned(4)));
+typedef const __attribute__((address_space(1))) u32x2_a4 global_u32x2_a4;
+typedef const __attribute__((address_space(1))) u32x3_a4 global_u32x3_a4;
 
 struct GlobalText {
     uintptr_t lo, hi;   // the text's bytes are [lo, hi) (absolute addresses)
@@ -446,19 +452,40 @@ __device__ __forceinline__ uint32_t gdword(const GlobalText &T, uintptr_t d) {
     return (d + 4u > T.lo && d < T.hi) ? *(global_u32 *)d : 0u;
 }
 
-// Hash (eq. (3)) of the q-gram that ends at absolute address e.
+// Hash (eq. (3)) of the q-gram that ends at absolute address e. The aligned
+// dwords holding it are read with one load when each of them holds a text
+// byte (everywhere but at the text's two ends), else one by one.
 template <int Q>
 __device__ __forceinline__ uint32_t ghash(const GlobalText &T, uintptr_t e, uint32_t s, uint32_t mask) {
     uint32_t v = 0;
     if constexpr (Q <= 4) {
         const uintptr_t p = e - 3u, a = p & ~uintptr_t(3);
-        const uint32_t w = __builtin_amdgcn_alignbyte(gdword(T, a + 4u), gdword(T, a), uint32_t(p & 3u));
+        uint32_t d0, d1;
+        if (a + 4u > T.lo && a + 4u < T.hi) {
+            const u32x2 d = *(global_u32x2_a4 *)a;
+            d0 = d.x;
+            d1 = d.y;
+        } else {
+            d0 = gdword(T, a);
+            d1 = gdword(T, a + 4u);
+        }
+        const uint32_t w = __builtin_amdgcn_alignbyte(d1, d0, uint32_t(p & 3u));
 #pragma unroll
         for (int k = Q - 1; k >= 0; --k) v = (v << s) + __builtin_amdgcn_ubfe(w, 8 * (4 - Q + k), 8);
     } else {
         const uintptr_t p = e - 7u, a = p & ~uintptr_t(3);
         const uint32_t sh = uint32_t(p & 3u);
-        const uint32_t d0 = gdword(T, a), d1 = gdword(T, a + 4u), d2 = gdword(T, a + 8u);
+        uint32_t d0, d1, d2;
+        if (a + 4u > T.lo && a + 8u < T.hi) {
+            const u32x3 d = *(global_u32x3_a4 *)a;
+            d0 = d.x;
+            d1 = d.y;
+            d2 = d.z;
+        } else {
+            d0 = gdword(T, a);
+            d1 = gdword(T, a + 4u);
+            d2 = gdword(T, a + 8u);
+        }
         const uint32_t lo = __builtin_amdgcn_alignbyte(d1, d0, sh);
         const uint32_t hi = __builtin_amdgcn_alignbyte(d2, d1, sh);
 #pragma unroll
@@ -469,6 +496,106 @@ __device__ __forceinline__ uint32_t ghash(const GlobalText &T, uintptr_t e, uint
         }
     }
     return v & mask;
+}
+
+typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
+typedef u32x4_v u32x4_a4 __attribute__((aligned(4)));
+typedef const __attribute__((address_space(1))) u32x4_a4 global_u32x4_a4;
+
+// The 16 text bytes ending at absolute address e, as four dwords (w[0]'s
+// lowest byte is e - 15, w[3]'s highest is e), read with one 16-byte and one
+// 4-byte load where every dword read holds a text byte, else dword by dword
+// (dwords with no text byte read as 0).
+__device__ __forceinline__ void gspan16(const GlobalText &T, uintptr_t e, uint32_t (&w)[4]) {
+    const uintptr_t p = e - 15u, a = p & ~uintptr_t(3);
+    uint32_t d[5];
+    if (a + 4u > T.lo && a + 16u < T.hi) {
+        const u32x4_v v = *(global_u32x4_a4 *)a;
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+        d[4] = *(global_u32 *)(a + 16u);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) d[i] = gdword(T, a + 4u * uint32_t(i));
+    }
+    const uint32_t sh = uint32_t(p & 3u);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+}
+
+// Hash (eq. (3)) of the q-gram that ends I * Q bytes before the end of a
+// 16-byte span (I * Q + Q <= 16).
+template <int Q, int I>
+__device__ __forceinline__ uint32_t span_hash(const uint32_t (&w)[4], uint32_t s, uint32_t mask) {
+    static_assert(I * Q + Q <= 16, "q-gram inside the span");
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = Q - 1; k >= 0; --k) {
+        constexpr int kEnd = 15 - I * Q;
+        const int b = kEnd - (Q - 1) + k;   // span position of byte k of the q-gram
+        v = (v << s) + __builtin_amdgcn_ubfe(w[b >> 2], 8 * (b & 3), 8);
+    }
+    return v & mask;
+}
+
+// Chain steps I..KS of an attempt whose q-grams lie in the span w (the
+// q-gram of step i ends i * Q bytes before the span's end). Returns true with
+// `next` set when a link is missing; false when the steps in the span are
+// used up or the walk reached the window start (then e < lo).
+template <int Q, int I, int KS, typename WT>
+__device__ __forceinline__ bool span_chain(const uint32_t (&w)[4], const PatternView &P, const WT *__restrict__ F,
+                                           int32_t lo, uint32_t &e, uint32_t &v, WT &z, uint32_t &next) {
+    if constexpr (I > KS) {
+        return false;
+    } else {
+        if (int32_t(e) < lo) return false;
+        const uint32_t vp = span_hash<Q, I>(w, P.s, P.mask);
+        const uint32_t ep = e - Q;
+        if (!linked(z, vp)) {
+            next = ep + P.m - Q + 1u;
+            return true;
+        }
+        e = ep;
+        v = vp;
+        z = F[vp];
+        return span_chain<Q, I + 1, KS, WT>(w, P, F, lo, e, v, z, next);
+    }
+}
+
+// One attempt of the searching loop at window end J (tile-relative; base =
+// absolute address of tile position 0) with the 16 bytes ending at J already
+// in w: the first word, then the chain of links towards the window start,
+// its first 16 / Q - 1 steps from w and the rest read in place. Returns the
+// next window end; after kLocalSteps links read in place the walk is handed
+// back (kParkedJ) with its position in (e, v, z). Marks candidates.
+template <int Q, typename WT>
+__device__ __forceinline__ uint32_t sparse_attempt(const GlobalText &T, uintptr_t base, const WT *__restrict__ F,
+                                                   const PatternView &P, uint32_t J, const uint32_t (&w)[4],
+                                                   uint32_t &e, uint32_t &v, WT &z, uint32_t *bitmap,
+                                                   uint32_t *any) {
+    constexpr int KS = 16 / Q - 1;   // chain steps inside the span
+    const uint32_t shift = P.m - Q + 1u;
+    v = span_hash<Q, 0>(w, P.s, P.mask);
+    z = F[v];
+    if (z == 0) return J + shift;   // no q-gram of x hashes here
+    const int32_t lo = int32_t(J) - int32_t(P.m) + 2 * Q;
+    e = J;
+    uint32_t next = 0;
+    if (span_chain<Q, 1, KS, WT>(w, P, F, lo, e, v, z, next)) return next;
+    int steps = kLocalSteps;
+    while (int32_t(e) >= lo) {
+        if (steps-- == 0) return kParkedJ;
+        const uint32_t ep = e - Q;
+        const uint32_t vp = ghash<Q>(T, base + ep, P.s, P.mask);
+        if (!linked(z, vp)) return ep + shift;
+        e = ep;
+        v = vp;
+        z = F[vp];
+    }
+    if (v == P.hv) mark(bitmap, J + 1u - P.m, any);
+    return J + 1u;
 }
 
 // A parked chain walk finished by the whole wavefront with the q-grams read
@@ -564,7 +691,7 @@ __device__ __forceinline__ TileResult verify_tile(const uint32_t *__restrict__ t
     return R;
 }
 
-template <int Q, typename WT, int K>
+template <int Q, typename WT, int K, bool WIDE = true>
 __device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t32, uint32_t tb,
                                                   const WT *__restrict__ F,
                                                   const uint32_t *__restrict__ x32,
@@ -574,7 +701,15 @@ __device__ __forceinline__ TileResult search_tile(const uint32_t *__restrict__ t
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     uint32_t *any = &misc[8 + (it & 1u)];
     {
-        const uint32_t lo = min(S, tid * seg), hi = min(S, lo + seg);
+        // WIDE: a lane's range holds at least two shifts (one per half): a
+        // first attempt whose word is empty already rules out a shift's
+        // worth of window ends, so narrower ranges would only repeat
+        // attempts. With long patterns only the first ranges hold windows;
+        // range r goes to lane r / 4 of wavefront r % 4, so those are spread
+        // over the workgroup's four wavefronts (and SIMDs).
+        const uint32_t span = WIDE ? max(seg, 2u * (P.m - Q + 1u)) : seg;
+        const uint32_t r = (lane << 2) | wid;
+        const uint32_t lo = min(S, r * span), hi = min(S, lo + span);
         const uint32_t jlo = lo + P.m - 1u, jhi = hi + P.m - 1u;
         const uint32_t jmid = jlo + ((jhi - jlo) >> 1);
         uint32_t J0 = jlo, J1 = jmid, myslot = kParkCap;

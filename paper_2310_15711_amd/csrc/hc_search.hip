@@ -217,14 +217,20 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
     const uint32_t tid = threadIdx.x;
     const uint32_t tile_words = A.tile / 32u;
     {
+        // table, pattern bytes (zero-padded to 16 bytes on the device, plus
+        // 32 zero bytes here) and a cleared bitmap, in 16-byte units
         const uint4 *src = reinterpret_cast<const uint4 *>(A.F);
         uint4 *dst = reinterpret_cast<uint4 *>(F);
         for (uint32_t i = tid; i < (A.table_bytes + 15u) / 16u; i += kBlock) dst[i] = src[i];
-        for (uint32_t i = tid; i < align16(A.m) + 32u; i += kBlock) x8[i] = i < A.m ? A.x[i] : 0;
-        for (uint32_t i = tid; i < tile_words; i += kBlock) bm[i] = 0u;
+        const uint4 *xs = reinterpret_cast<const uint4 *>(A.x);
+        uint4 *xd = reinterpret_cast<uint4 *>(x8);
+        const uint32_t xw = align16(A.m) / 16u;
+        for (uint32_t i = tid; i < xw + 2u; i += kBlock) xd[i] = i < xw ? xs[i] : uint4{0u, 0u, 0u, 0u};
+        uint4 *bm4 = reinterpret_cast<uint4 *>(bm);
+        for (uint32_t i = tid; i < tile_words / 4u; i += kBlock) bm4[i] = uint4{0u, 0u, 0u, 0u};
         if (tid == 0) misc[8] = misc[9] = 0u;
     }
-    __syncthreads();
+    lds_barrier();
     const GlobalText T{reinterpret_cast<uintptr_t>(A.y), reinterpret_cast<uintptr_t>(A.y) + A.n};
     const uint32_t shift = A.m - uint32_t(Q) + 1u;
     const PatternView P{A.m, uint32_t(Q), A.s, A.mask, A.hv};
@@ -246,57 +252,22 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
         WT z = 0;
         while (__ballot(J < Jend) != 0ull) {   // wavefront-uniform
             if (J < Jend && !parked) {
-                uint32_t vv[4];
-                WT zz[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint32_t Jn = J + uint32_t(i) * shift;
-                    vv[i] = ghash<Q>(T, base + (Jn < Jend ? Jn : J), A.s, A.mask);
-                    zz[i] = F[vv[i]];
+                // the 16 bytes ending at this attempt's window end and, when
+                // it lies in the lane's range, at the next one (where an empty
+                // word would move it), loaded together
+                uint32_t w0[4], w1[4];
+                const uint32_t J1 = J + shift;
+                gspan16(T, base + J, w0);
+                if (J1 < Jend) gspan16(T, base + J1, w1);
+                uint32_t next = sparse_attempt<Q, WT>(T, base, F, P, J, w0, e, v, z, bm, any);
+                if (next == J1 && J1 < Jend) {   // the next attempt's bytes are already here
+                    J = J1;
+                    next = sparse_attempt<Q, WT>(T, base, F, P, J, w1, e, v, z, bm, any);
                 }
-                int first = 4;
-#pragma unroll
-                for (int i = 3; i >= 0; --i)
-                    if (zz[i] != 0 && J + uint32_t(i) * shift < Jend) first = i;
-                if (first == 4) {
-                    J += 4u * shift;   // four empty words in a row
-                } else {
-                    v = vv[0];
-                    z = zz[0];
-#pragma unroll
-                    for (int i = 1; i < 4; ++i)
-                        if (first == i) {
-                            v = vv[i];
-                            z = zz[i];
-                        }
-                    J += uint32_t(first) * shift;
-                    // chain walk towards the window start (as in the searching loop)
-                    const int32_t lo_e = int32_t(J) - int32_t(A.m) + 2 * Q;
-                    e = J;
-                    uint32_t next = J + 1u;
-                    bool broken = false;
-                    int steps = kLocalSteps;
-                    while (int32_t(e) >= lo_e) {
-                        if (steps-- == 0) {
-                            parked = true;
-                            break;
-                        }
-                        const uint32_t ep = e - Q;
-                        const uint32_t vp = ghash<Q>(T, base + ep, A.s, A.mask);
-                        if (!linked(z, vp)) {
-                            next = ep + shift;
-                            broken = true;
-                            break;
-                        }
-                        e = ep;
-                        v = vp;
-                        z = F[vp];
-                    }
-                    if (!parked) {
-                        if (!broken && v == A.hv) mark(bm, J + 1u - A.m, any);
-                        J = next;
-                    }
-                }
+                if (next == kParkedJ)
+                    parked = true;   // J stays the window end of the parked walk
+                else
+                    J = next;
             }
             // parked walks of this wavefront, one at a time, all lanes
             uint64_t pm = __ballot(parked);

@@ -141,6 +141,11 @@ class _Handle:
         self.p, self.handle, self.params = p, p.handle, params
 
 
+# a smaller grid for the texts that test tile and segment edges: every q,
+# heavy collisions (alpha 3) and a usual table (alpha 12, w 32)
+SMALL_GRID = [(q, a, w) for (a, w) in ((3, 16), (12, 32)) for q in range(1, 7)]
+
+
 @pytest.fixture(scope="module")
 def dev():
     import torch
@@ -149,19 +154,39 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("enc", ENCODINGS)
-def test_exhaustive_binary_every_launch(dev, enc):
+@pytest.fixture(scope="module")
+def handles():
+    """Pattern handles per (encoding, grid), built once for all launches."""
     pats = binary_patterns()
-    lut = np.array(enc, dtype=np.uint8)
-    handles = [[_Handle(B.hc_preprocess(lut[p].tobytes(), prm), prm) for prm in GRID if prm[0] <= p.size]
-               for p in pats]
+    cache = {}
+
+    def get(enc, grid):
+        key = (enc, tuple(grid))
+        if key not in cache:
+            lut = np.array(enc, dtype=np.uint8)
+            cache[key] = [[_Handle(B.hc_preprocess(lut[p].tobytes(), prm), prm) for prm in grid
+                           if prm[0] <= p.size] for p in pats]
+        return cache[key]
+
+    return pats, get
+
+
+@pytest.mark.parametrize("launch", LAUNCHES, ids=[x[0] for x in LAUNCHES])
+def test_exhaustive_binary(dev, handles, launch):
+    """One launch shape: every binary text up to length 12 and the de Bruijn
+    text with the full (q, alpha, w) grid; texts ending at and inside tile
+    and segment boundaries, and the short texts again under two more byte
+    encodings, with the smaller grid."""
+    pats, get = handles
+    g = np.random.default_rng([231015711, 7, launch[1], launch[3]])
     short, dbs = all_short_texts(), de_bruijn()
-    g = np.random.default_rng([231015711, 7, enc[0]])
+    jobs = [("all texts of length 1..12", short, ENCODINGS[0], GRID),
+            ("de Bruijn B(2,12)", dbs, ENCODINGS[1], GRID)]
+    for t in boundary_texts(launch[1], launch[3], g):
+        jobs.append((f"{t.size} bytes", t, ENCODINGS[2], SMALL_GRID))
+    jobs.append(("all texts of length 1..12", short, ENCODINGS[3], SMALL_GRID))
     launches = 0
-    for launch in LAUNCHES:
-        texts = [("all texts of length 1..12", short), ("de Bruijn B(2,12)", dbs)]
-        texts += [(f"{t.size} bytes", t) for t in boundary_texts(launch[1], launch[3], g)]
-        for name, t in texts:
-            announce("exhaustive single", launch[0], enc, name)
-            launches += run_text(t, enc, pats, handles, launch, dev)
-    announce("exhaustive single launches", enc, launches)
+    for name, t, enc, grid in jobs:
+        announce("exhaustive single", launch[0], enc, name)
+        launches += run_text(t, enc, pats, get(enc, grid), launch, dev)
+    announce("exhaustive single launches", launch[0], launches)
