@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--batch-texts", type=int, default=64)
     ap.add_argument("--batch-patterns", type=int, default=4096)
     ap.add_argument("--batch-params", default=None, help="q,alpha,w for the batch plan (0 = library choice)")
+    ap.add_argument("--no-batch-tune", action="store_true", help="batched workload: skip hc_batch_autotune")
+    ap.add_argument("--batch-tune-pairs", type=int, default=22000,
+                    help="batched workload: pairs sampled by hc_batch_autotune")
     ap.add_argument("--batch-oracle-pairs", type=int, default=1000,
                     help="batched workload: seeded pairs compared with the oracle")
     ap.add_argument("--serve-oracle", type=int, default=1000,
@@ -244,6 +247,21 @@ def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
     print(json.dumps(tj))
 
 
+# int32 lane-ops per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def alu_roofline(ops, seconds, kernel):
+    """Roofline of a run bound by integer ALU work: the searching phase's own
+    operations (per pattern and text byte, (2q + 6) / (m - q + 1): one attempt
+    per shift, each hashing q bytes and testing one word) over the run time."""
+    achieved = ops / seconds / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+            "unit": "Tops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+            "kernel": kernel, "ops_per_run": round(ops),
+            "ops_model": "per (pattern, text byte): (2q + 6) / (m - q + 1) int32 lane-ops"}
+
+
 def method_read_fractions(pats, infos):
     """Per launch: the share of the text's 128-byte lines the method reads
     (1 for m <= 32; else from profiles/hc_method_bytes.json; None when the
@@ -337,8 +355,16 @@ def run_batched(args):
     pair_bytes = int(sizes[pt].sum())
     log(f"batched inputs in {time.time() - t0:.1f}s: {len(b.texts)} texts, {int(sizes.sum())} bytes, "
         f"{len(b.patterns)} patterns, {len(pp)} pairs, {pair_bytes / 1e12:.3f} TB pattern x text")
-    t0 = time.time()
     bparams = tuple(int(v) for v in args.batch_params.split(",")) if args.batch_params else None
+    btune, btune_s = None, 0.0
+    if bparams is None and not args.no_batch_tune:
+        # table shape, lane segment, group size and workgroups per CU of the
+        # batched kernel, timed on an evenly spaced sample of this batch's pairs
+        t0 = time.time()
+        btune = B.hc_batch_autotune(d_text, off, b.patterns, pp, pt, max_pairs=args.batch_tune_pairs)
+        btune_s = time.time() - t0
+        log(f"batched autotune in {btune_s:.1f}s: {btune}")
+    t0 = time.time()
     plan = B.BatchPlan(d_text, off, b.patterns, pp, pt, params=bparams)
     plan_s = time.time() - t0
     pair_off = torch.empty(len(pp) + 1, dtype=torch.int64, device=dev)
@@ -359,6 +385,16 @@ def run_batched(args):
         times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
     value = pair_bytes / (ms * 1e-3) / 1e9
+    # integer work the method itself does on the plan's pairs, against the
+    # chip's int32 lane-op rate (the batched kernel is bound by ALU and LDS,
+    # not HBM: each staged tile serves a whole group of patterns)
+    qa, aa, wa = bparams if bparams else (0, 12, 16)
+    qs = [B.hc_pattern_info(B.hc_preprocess(x, (min(qa, len(x)), aa or 12, wa or 16)))["q"]
+          for x in b.patterns]   # the q the plan gives each pattern
+    ms_pat = np.array([len(x) for x in b.patterns], dtype=np.float64)
+    per_byte = (2.0 * np.array(qs) + 6.0) / (ms_pat - np.array(qs) + 1.0)
+    ops = float(np.sum(sizes[pt] * per_byte[pp]))
+    roof = alu_roofline(ops, ms * 1e-3, "hc_batch_kernel + CSR kernels (one plan run)")
     # oracle parity: a seeded sample of pairs, complete lists
     from oracle import hc_oracle as O
 
@@ -414,8 +450,10 @@ def run_batched(args):
                                f"64 KiB-16 MiB, sigma 4/20/64), {len(b.patterns)} patterns "
                                f"(m log-uniform 4..1024), {len(pp)} pairs, one plan run per step",
                    "pattern_x_text_bytes": pair_bytes, "occurrences": int(total),
-                   "plan_create_s": round(plan_s, 2)},
+                   "plan_create_s": round(plan_s, 2),
+                   "autotune": ({"seconds": round(btune_s, 1), "choice": btune} if btune else None)},
         "parity": parity,
+        "roofline": roof,
         "per_pattern_launches": per_pattern,
         "speedup_vs_per_pattern_gpu_busy": (round(value / per_pattern["gbps_gpu_busy"], 2)
                                             if per_pattern else None),
@@ -822,9 +860,10 @@ def main():
         torch.cuda.empty_cache()
         bt = run_batched(args)
         rec["batched"] = {"value": bt["value"], "unit": "GB/s", "config": bt["config"],
-                          "parity": bt["parity"],
+                          "parity": bt["parity"], "roofline": bt["roofline"],
                           "per_pattern_launches": bt["per_pattern_launches"],
                           "speedup_vs_per_pattern_gpu_busy": bt["speedup_vs_per_pattern_gpu_busy"]}
+        B.hc_autotune_reset()   # the served leg runs on the library's defaults
         rec["served"] = run_served(args)
     print(json.dumps(rec), flush=True)
 

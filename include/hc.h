@@ -288,6 +288,30 @@ hc_status hc_batch_plan_run(hc_batch_plan *plan, int64_t *d_pos, int64_t cap,
 void hc_batch_plan_free(hc_batch_plan *plan);
 
 /*
+ * hc_batch_autotune -- measure which table shape (alpha, w), lane segment,
+ * patterns per staged tile (group) and resident workgroups per compute unit
+ * make batch plans fastest on this batch (on an evenly spaced sample of at
+ * most max_pairs of its pairs), and make them the library's choice for batch
+ * plans, hc_search_batched and servers created afterwards with params NULL
+ * (or alpha and w left at 0); process-wide, the last tuning wins, and
+ * hc_autotune_reset forgets it. q stays per pattern (hc_autotune's tuning or
+ * the built-in priors). out (may be NULL) receives the choice and its
+ * pattern x text GB/s on the sample. Builds and runs several plans on
+ * `stream` and synchronises it; allocates their outputs. The choice never
+ * changes results. Errors: HC_EINVAL on bad arguments or an empty batch.
+ */
+typedef struct {
+    hc_params params;     /* alpha and w chosen (q = 0: per pattern)          */
+    int32_t segment;      /* window starts per lane of the batched kernel      */
+    int32_t group;        /* patterns searched per staged tile                 */
+    int32_t wg_per_cu;    /* cap on resident workgroups per CU (0 = none)      */
+    double gbps;          /* pattern x text bytes per second on the sample     */
+} hc_batch_tuning;
+
+hc_status hc_batch_autotune(const hc_batch *batch, int64_t max_pairs, hc_batch_tuning *out,
+                            void *stream);
+
+/*
  * Serving: continuous batching of search requests against resident texts.
  * hc_serve_create registers n_texts device texts (caller-owned, written
  * before the call, must outlive the server), a device-memory budget in bytes

@@ -27,7 +27,7 @@ EXPORTED = (
     "hc_search_batched", "hc_batch_plan_create", "hc_batch_plan_run", "hc_batch_plan_free",
     "hc_serve_create", "hc_serve_submit", "hc_serve_poll", "hc_serve_next_done",
     "hc_serve_stats", "hc_serve_destroy", "hc_strerror", "hc_autotune", "hc_autotune_reset",
-    "hc_preprocess_many", "hc_search_async_noalloc",
+    "hc_preprocess_many", "hc_search_async_noalloc", "hc_batch_autotune",
 )
 
 
@@ -49,6 +49,11 @@ class hc_launch(ctypes.Structure):
 class hc_tuning(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("params", hc_params), ("launch", hc_launch),
                 ("gbps", ctypes.c_double)]
+
+
+class hc_batch_tuning(ctypes.Structure):
+    _fields_ = [("params", hc_params), ("segment", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("gbps", ctypes.c_double)]
 
 
 class hc_batch(ctypes.Structure):
@@ -93,6 +98,7 @@ def lib():
         "hc_autotune_reset": (None, []),
         "hc_preprocess_many": (i32, [p, p, i32, p, p, i64, p, p, p]),
         "hc_search_async_noalloc": (i32, [p, p, i64, p, i64, p, p, p]),
+        "hc_batch_autotune": (i32, [P(hc_batch), i64, P(hc_batch_tuning), p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -274,6 +280,18 @@ def hc_search_batched(d_text, text_off: Sequence[int], patterns: Sequence[bytes]
                                  _stream_ptr(stream))
     _check(st, "hc_search_batched", ok=(HC_OK, HC_EOVERFLOW))
     return st, total.value
+
+
+def hc_batch_autotune(d_text, text_off, patterns, pair_pat, pair_text, max_pairs: int = 1 << 20,
+                      stream=None) -> dict:
+    """Tunes the batched kernel's table shape and launch shape on this batch
+    and installs the choice for plans created afterwards with params None."""
+    b, _keep = _make_batch(d_text, text_off, patterns, pair_pat, pair_text)
+    out = hc_batch_tuning()
+    _check(lib().hc_batch_autotune(ctypes.byref(b), int(max_pairs), ctypes.byref(out), _stream_ptr(stream)),
+           "hc_batch_autotune")
+    return {"alpha": out.params.alpha, "w": out.params.w, "segment": out.segment, "group": out.group,
+            "wg_per_cu": out.wg_per_cu, "gbps": out.gbps}
 
 
 class BatchPlan:

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "hc_batch.h"
 #include "hc_internal.h"
 #include "hc_runtime.h"
 
@@ -193,4 +194,121 @@ extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *m
 
 extern "C" void hc_autotune_reset(void) {
     for (int b = 0; b < kBuckets; ++b) set_tuned(int64_t(1) << b, Tuned{});
+    set_batch_knobs(nullptr);
+}
+
+// ----------------------------------------------------------------------------
+// Batched kernel: table shape (alpha, w), tile segment, patterns per staged
+// tile and resident workgroups per compute unit, timed on the caller's own
+// batch (or an evenly spaced sample of its pairs).
+// ----------------------------------------------------------------------------
+
+namespace hc {
+namespace {
+
+struct BatchCand {
+    BatchKnobs k;
+    double ms = 1e30;
+};
+
+// Median-free minimum of two timed runs of a plan built with knobs k.
+hc_status time_batch(const hc_batch &b, const BatchKnobs &k, hipStream_t s, double *ms) {
+    hc_batch_plan *plan = nullptr;
+    hc_status st = plan_create(&b, nullptr, k, &plan);
+    if (st != HC_OK) return st;
+    int64_t *d_off = nullptr, *d_pos = nullptr;
+    int64_t total = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d_off), size_t(b.n_pairs + 1) * 8) != hipSuccess) st = HC_ENOMEM;
+    if (st == HC_OK) {
+        st = hc_batch_plan_run(plan, nullptr, 0, d_off, &total, s);   // counts only
+        if (st == HC_EOVERFLOW) st = HC_OK;
+    }
+    if (st == HC_OK && hipMalloc(reinterpret_cast<void **>(&d_pos), size_t(std::max<int64_t>(total, 1)) * 8) != hipSuccess)
+        st = HC_ENOMEM;
+    if (st == HC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = HC_EHIP;
+    double best = 1e30;
+    for (int r = 0; r < 3 && st == HC_OK; ++r) {   // the first run builds the graph
+        int64_t t2 = 0;
+        if (hipEventRecord(e0, s) != hipSuccess) st = HC_EHIP;
+        if (st == HC_OK) st = hc_batch_plan_run(plan, d_pos, total, d_off, &t2, s);
+        if (st == HC_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            st = HC_EHIP;
+        float f = 0;
+        if (st == HC_OK && hipEventElapsedTime(&f, e0, e1) != hipSuccess) st = HC_EHIP;
+        if (st == HC_OK && r > 0) best = std::min(best, double(f));
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_pos);
+    (void)hipFree(d_off);
+    hc_batch_plan_free(plan);
+    *ms = best;
+    return st;
+}
+
+}  // namespace
+}  // namespace hc
+
+extern "C" hc_status hc_batch_autotune(const hc_batch *b, int64_t max_pairs, hc_batch_tuning *out, void *stream) {
+    if (!b || max_pairs < 1 || b->n_pairs < 1) return HC_EINVAL;
+    if (!device_info().ok) return HC_EHIP;
+    hipStream_t s = hipStream_t(stream);
+    // an evenly spaced sample of the pairs (every pair when there are few)
+    std::vector<int32_t> pp, pt;
+    const int64_t step = (b->n_pairs + max_pairs - 1) / max_pairs;
+    for (int64_t k = 0; k < b->n_pairs; k += step) {
+        pp.push_back(b->pair_pat[k]);
+        pt.push_back(b->pair_text[k]);
+    }
+    hc_batch sub = *b;
+    sub.pair_pat = pp.data();
+    sub.pair_text = pt.data();
+    sub.n_pairs = int64_t(pp.size());
+    // phase 1: table shape x segment; phase 2: the best two with other
+    // group sizes and workgroup caps
+    static const int shapes[][2] = {{10, 16}, {11, 16}, {12, 16}, {13, 16}, {12, 32}};
+    static const uint32_t segs[] = {64, 80, 100};
+    std::vector<BatchCand> cs;
+    hc_status st = HC_OK;
+    for (const auto &aw : shapes)
+        for (uint32_t seg : segs) {
+            BatchCand c;
+            c.k.alpha = aw[0];
+            c.k.w = aw[1];
+            c.k.seg = seg;
+            st = time_batch(sub, c.k, s, &c.ms);
+            if (st == HC_EINVAL) {   // shape does not fit (LDS): skip it
+                st = HC_OK;
+                continue;
+            }
+            if (st != HC_OK) return st;
+            cs.push_back(c);
+        }
+    if (cs.empty()) return HC_EINVAL;
+    std::sort(cs.begin(), cs.end(), [](const BatchCand &x, const BatchCand &y) { return x.ms < y.ms; });
+    BatchCand best = cs[0];
+    for (size_t i = 0; i < std::min<size_t>(2, cs.size()); ++i)
+        for (uint32_t group : {32u, 64u, 128u})
+            for (uint32_t wg : {0u, 2u}) {
+                BatchCand c = cs[i];
+                c.k.group = group;
+                c.k.wg_per_cu = wg;
+                if (group == 128u && wg == 0u) continue;   // timed in phase 1
+                st = time_batch(sub, c.k, s, &c.ms);
+                if (st != HC_OK) return st;
+                if (c.ms < best.ms) best = c;
+            }
+    set_batch_knobs(&best.k);
+    if (out) {
+        double bytes = 0;
+        for (size_t k = 0; k < pp.size(); ++k)
+            bytes += double(b->text_off[pt[k] + 1] - b->text_off[pt[k]]);
+        out->params = hc_params{0, best.k.alpha, best.k.w};
+        out->segment = int32_t(best.k.seg);
+        out->group = int32_t(best.k.group);
+        out->wg_per_cu = int32_t(best.k.wg_per_cu);
+        out->gbps = bytes / (best.ms * 1e-3) / 1e9;
+    }
+    return HC_OK;
 }

@@ -52,7 +52,7 @@ struct BatchHost {
 
 // Device side of a batch: geometry, uploaded descriptors and result buffers.
 struct BatchDev {
-    uint32_t tile = 0, seg = 100, table_bytes = 0, max_m = 1, w = 16, lds = 0, max_grid = 0;
+    uint32_t tile = 0, seg = 100, table_bytes = 0, max_m = 1, w = 16, lds = 0, max_grid = 0, group = 128;
     uint32_t n_pairs = 0, n_items = 0, grid = 0, nb = 0;
     uint64_t n_entries = 0, scratch_cap = 0;
     const uint8_t *Fs = nullptr;   // table_bytes per pattern index
@@ -63,11 +63,32 @@ struct BatchDev {
     DeviceBuf views, pats, items, glist, pair_base, counts, toff, temp, ctl, tot, bsum, grand;
 };
 
-// Common table shape of a batch (w in {16, 32}; tables up to 16 KiB).
-hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &table_bytes);
+// Launch shape of the batched kernel: table shape for fields the caller
+// leaves at 0, window starts per lane (tile = 256 * seg, reduced to fit
+// LDS and the staging registers), patterns per staged tile, and a cap on
+// resident workgroups per compute unit (0 = as many as fit).
+struct BatchKnobs {
+    int alpha = 12, w = 16;
+    uint32_t seg = 100, group = 128, wg_per_cu = 0;
+};
+
+// The library's current choice (hc_batch_autotune's winner, else the
+// defaults above); process-wide.
+BatchKnobs batch_knobs();
+void set_batch_knobs(const BatchKnobs *k);   // null = back to the defaults
+
+// Common table shape of a batch (w in {16, 32}; tables up to 16 KiB); fields
+// of params left at 0 come from the knobs.
+hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &table_bytes,
+                      const BatchKnobs &k = batch_knobs());
+
+// hc_batch_plan_create with explicit knobs.
+hc_status plan_create(const hc_batch *b, const hc_params *params, const BatchKnobs &knobs,
+                      hc_batch_plan **out);
 
 // Tile size, LDS and grid bound for patterns up to max_m bytes.
-hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint32_t w);
+hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint32_t w,
+                         const BatchKnobs &k = batch_knobs());
 
 // Preprocesses np patterns (CSR pat/pat_off) into packed tables and bytes.
 hc_status pack_patterns(const uint8_t *pat, const int64_t *pat_off, int32_t np, const hc_params *params,
@@ -115,6 +136,5 @@ hc_status scatter_patterns(const uint8_t *d_src, const uint32_t *d_slots, uint32
 // every position but whose output capacity was too small).
 hc_status batch_emit(BatchDev &D, int64_t *d_pos, int64_t cap, const int64_t *d_pair_off, hipStream_t s);
 
-constexpr uint32_t kBatchGroup = 128;   // patterns searched per staged tile
 
 }  // namespace hc

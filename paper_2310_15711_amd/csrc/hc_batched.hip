@@ -53,7 +53,10 @@ __device__ __forceinline__ TileResult batch_tile(const uint32_t *t32, uint32_t t
                                                  const uint32_t *x32, const PatternView &P,
                                                  uint32_t S, uint32_t seg, uint32_t *bm, Parked *park,
                                                  uint32_t *misc, uint32_t &it, uint32_t &round) {
-    return search_tile<Q, WT, K>(t32, tb, F, x32, P, S, seg, bm, park, misc, it, round);
+    // ranges of `seg` starts per lane: here a long pattern's search overlaps
+    // the loads of the group's next table, which it hides best when all
+    // lanes take part
+    return search_tile<Q, WT, K, false>(t32, tb, F, x32, P, S, seg, bm, park, misc, it, round);
 }
 
 template <typename WT, int K>
@@ -462,9 +465,22 @@ static hc_status batch_occupancy(uint32_t lds, int *per_cu) {
     return HC_OK;
 }
 
-hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &table_bytes) {
-    w = params && params->w ? params->w : 16;
-    alpha = params && params->alpha ? params->alpha : 12;
+static std::mutex g_knobs_mu;
+static BatchKnobs g_knobs;
+
+BatchKnobs batch_knobs() {
+    std::lock_guard<std::mutex> g(g_knobs_mu);
+    return g_knobs;
+}
+
+void set_batch_knobs(const BatchKnobs *k) {
+    std::lock_guard<std::mutex> g(g_knobs_mu);
+    g_knobs = k ? *k : BatchKnobs{};
+}
+
+hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &table_bytes, const BatchKnobs &k) {
+    w = params && params->w ? params->w : k.w;
+    alpha = params && params->alpha ? params->alpha : k.alpha;
     if ((w != 16 && w != 32) || alpha < 1 || alpha > alpha_max(w)) return HC_EINVAL;
     table_bytes = uint32_t((size_t(1) << alpha) * size_t(w / 8));
     table_bytes = std::max<uint32_t>(16, (table_bytes + 15u) & ~15u);
@@ -472,14 +488,15 @@ hc_status batch_shape(const hc_params *params, int &alpha, int &w, uint32_t &tab
     return HC_OK;
 }
 
-hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint32_t w) {
+hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint32_t w, const BatchKnobs &k) {
     const DeviceInfo &di = device_info();
     if (!di.ok) return HC_EHIP;
     D.max_m = std::max<uint32_t>(max_m, 1);
     D.table_bytes = table_bytes;
     D.w = w;
-    // tiles as large as LDS allows
-    D.seg = 100;
+    D.group = std::max<uint32_t>(1, k.group);
+    // tiles of the knobs' size, or as large as LDS and the staging allow
+    D.seg = std::max<uint32_t>(8, std::min<uint32_t>(k.seg, 100));
     D.tile = kThreads * D.seg;
     LdsLayout L = lds_layout(D.tile, D.max_m, D.table_bytes, 0);
     while ((L.total > di.max_lds_per_block || D.tile + D.max_m - 1u > stage_limit(kThreads)) && D.seg > 8) {
@@ -492,6 +509,7 @@ hc_status batch_geometry(BatchDev &D, uint32_t max_m, uint32_t table_bytes, uint
     int per_cu = 1;
     hc_status st = w == 16 ? batch_occupancy<uint16_t>(D.lds, &per_cu) : batch_occupancy<uint32_t>(D.lds, &per_cu);
     if (st != HC_OK) return st;
+    if (k.wg_per_cu > 0) per_cu = std::min<int>(per_cu, int(k.wg_per_cu));
     D.max_grid = uint32_t(di.cus) * uint32_t(per_cu);
     return HC_OK;
 }
@@ -769,6 +787,13 @@ struct hc_batch_plan {
 extern "C" {
 
 hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_batch_plan **out) {
+    return hc::plan_create(b, params, hc::batch_knobs(), out);
+}
+
+}  // extern "C"
+
+hc_status hc::plan_create(const hc_batch *b, const hc_params *params, const BatchKnobs &knobs,
+                          hc_batch_plan **out) {
     if (!out) return HC_EINVAL;
     *out = nullptr;
     if (!b || b->n_pairs < 0 || b->n_texts < 0 || b->n_pats < 0) return HC_EINVAL;
@@ -789,7 +814,7 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
     if (!P) return HC_ENOMEM;
     int alpha = 0, w = 0;
     uint32_t table_bytes = 0;
-    hc_status st = batch_shape(params, alpha, w, table_bytes);
+    hc_status st = batch_shape(params, alpha, w, table_bytes, knobs);
     if (st != HC_OK) return st;
     // common table shape for the batch; q per pattern
     BatchHost H;
@@ -798,7 +823,7 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
     if ((st = pack_patterns(b->pat, b->pat_off, b->n_pats, params, alpha, w, table_bytes, H.pats, Fh, Xh,
                             max_m, false)) != HC_OK)
         return st;
-    if ((st = batch_geometry(P->D, max_m, table_bytes, uint32_t(w))) != HC_OK) return st;
+    if ((st = batch_geometry(P->D, max_m, table_bytes, uint32_t(w), knobs)) != HC_OK) return st;
     H.views.resize(size_t(b->n_texts));
     for (int32_t t = 0; t < b->n_texts; ++t) {
         const uint64_t len = uint64_t(b->text_off[t + 1] - b->text_off[t]);
@@ -806,7 +831,7 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
     }
     std::vector<std::pair<uint32_t, uint32_t>> pairs(size_t(b->n_pairs));
     for (int64_t k = 0; k < b->n_pairs; ++k) pairs[k] = {uint32_t(b->pair_pat[k]), uint32_t(b->pair_text[k])};
-    batch_build(H, pairs, P->D.tile, kBatchGroup);
+    batch_build(H, pairs, P->D.tile, P->D.group);
     hipStream_t s = nullptr;
     if ((st = P->xpool.upload(Xh.data(), Xh.size(), s)) != HC_OK) return st;
     // the word vectors are built on the device from the uploaded pattern bytes
@@ -832,6 +857,8 @@ hc_status hc_batch_plan_create(const hc_batch *b, const hc_params *params, hc_ba
     *out = P.release();
     return HC_OK;
 }
+
+extern "C" {
 
 void hc_batch_plan_free(hc_batch_plan *p) { delete p; }
 

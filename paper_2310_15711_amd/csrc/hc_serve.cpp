@@ -149,6 +149,7 @@ struct hc_server {
     uint64_t next_id = 1;
     std::deque<std::shared_ptr<Request>> pending;
     std::vector<std::shared_ptr<Request>> active;   // by slot (null = free)
+    std::vector<int32_t> free_slots;                // the null entries of `active`
     std::unordered_map<uint64_t, std::shared_ptr<Request>> by_id;
     std::deque<uint64_t> done_q;   // completed ids not yet taken by hc_serve_next_done
     uint64_t used_bytes = 0;
@@ -179,14 +180,9 @@ struct hc_server {
                 complete(*r, Clock::now());
                 continue;
             }
-            if (used_bytes + per_request > budget) break;
-            int32_t slot = -1;
-            for (uint32_t i = 0; i < slots; ++i)
-                if (!active[i]) {
-                    slot = int32_t(i);
-                    break;
-                }
-            if (slot < 0) break;
+            if (used_bytes + per_request > budget || free_slots.empty()) break;
+            const int32_t slot = free_slots.back();
+            free_slots.pop_back();
             pending.pop_front();
             r->slot = slot;
             r->to_issue = r->to_take = t.chunks;
@@ -266,7 +262,7 @@ bool hc_server::build(Step &S, std::vector<std::shared_ptr<Request>> &uploads, b
     if (bucket != S.D.max_m || S.D.tile == 0) {
         if (batch_geometry(S.D, bucket, table_bytes, uint32_t(w)) != HC_OK) S.D.tile = 0;
     }
-    if (S.D.tile) batch_build(H, pairs, S.D.tile, kBatchGroup);
+    if (S.D.tile) batch_build(H, pairs, S.D.tile, S.D.group);
     return true;
 }
 
@@ -382,6 +378,7 @@ void hc_server::finish(Step &S, hc_status st) {
             if (r.wrapped) std::rotate(r.pos.begin(), r.pos.begin() + ptrdiff_t(r.wrap_at), r.pos.end());
             complete(r, now);
             active[r.slot] = nullptr;
+            free_slots.push_back(r.slot);
             used_bytes -= per_request;
         }
     }
@@ -472,6 +469,7 @@ hc_status hc_serve_create(const uint8_t *const *d_texts, const int64_t *n, int32
     if (S->budget < S->per_request) return HC_EINVAL;
     S->slots = uint32_t(std::min<uint64_t>(kMaxSlots, S->budget / S->per_request));
     S->active.assign(S->slots, nullptr);
+    for (uint32_t i = S->slots; i-- > 0;) S->free_slots.push_back(int32_t(i));   // slot 0 first
     if (S->Fpool.ensure(size_t(S->slots) * S->table_bytes) != HC_OK ||
         S->xpool.ensure(size_t(S->slots) * kXStride + 64) != HC_OK ||
         S->patpool.ensure(size_t(S->slots) * sizeof(BPat)) != HC_OK)

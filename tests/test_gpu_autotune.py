@@ -78,3 +78,43 @@ def test_autotune_choices_are_used_and_exact(text):
             assert np.array_equal(pos[po[k]:po[k + 1]], w), pairs[k]
     finally:
         B.hc_autotune_reset()
+
+
+def test_batch_autotune_choice_is_used_and_exact():
+    """hc_batch_autotune on a batch of the batched workload's shape: a valid
+    choice, installed for plans and servers created afterwards, and the
+    plans built with it give the oracle's lists."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    b = W.batched_config(n_texts=12, n_patterns=300, median=1 << 20, lo=64 << 10, hi=4 << 20)
+    off = np.zeros(len(b.texts) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([t.size for t in b.texts])
+    d_text = torch.from_numpy(np.concatenate(b.texts)).to(dev)
+    pp, pt = b.pairs[:, 0].copy(), b.pairs[:, 1].copy()
+    try:
+        announce("batch autotune", len(pp))
+        t = B.hc_batch_autotune(d_text, off, b.patterns, pp, pt, max_pairs=800)
+        assert (t["alpha"], t["w"]) in {(10, 16), (11, 16), (12, 16), (13, 16), (12, 32)}
+        assert t["segment"] in (64, 80, 100) and t["group"] in (32, 64, 128) and t["wg_per_cu"] in (0, 2)
+        assert t["gbps"] > 0
+        plan = B.BatchPlan(d_text, off, b.patterns, pp, pt)
+        d_off = torch.empty(len(pp) + 1, dtype=torch.int64, device=dev)
+        st, total = plan.run(torch.empty(0, dtype=torch.int64, device=dev), d_off)
+        d_pos = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+        st, total = plan.run(d_pos, d_off)
+        assert st == B.HC_OK
+        po, pos = d_off.cpu().numpy(), d_pos.cpu().numpy()
+        g = np.random.default_rng(5)
+        for k in np.sort(g.choice(len(pp), size=min(400, len(pp)), replace=False)):
+            want = O.occurrences(b.patterns[int(pp[k])], b.texts[int(pt[k])])
+            assert np.array_equal(pos[po[k]:po[k + 1]], want), int(k)
+        # a server created now uses the tuned table shape; results unchanged
+        srv = B.Server([d_text[int(off[i]):int(off[i + 1])] for i in range(3)], 64 << 20)
+        ids = [srv.submit(i % 3, b.patterns[i]) for i in range(0, 60, 3)]
+        for j, rid in enumerate(ids):
+            i = 3 * j
+            assert np.array_equal(srv.result(rid), O.occurrences(b.patterns[i], b.texts[i % 3]))
+        srv.close()
+    finally:
+        B.hc_autotune_reset()
