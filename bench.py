@@ -90,6 +90,11 @@ def parse():
     ap.add_argument("--summarize", nargs=4, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "CALIB_PREFIX"),
                     help="turn rocprofv3 outputs into profiles/ summaries and traffic.json")
     ap.add_argument("--summary-cmd", default="", help="command lines quoted in the summary")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("PMC_DIR", "NAME", "TITLE"),
+                    help="write profiles/NAME.md: per-instance SQ counter means of a rocprofv3 --pmc run")
+    ap.add_argument("--per-unit", type=float, default=None,
+                    help="with --summarize-counters: units (e.g. windows) per dispatch")
+    ap.add_argument("--unit", default="window", help="with --summarize-counters: the unit's name")
     return ap.parse_args()
 
 
@@ -183,6 +188,42 @@ def summarize_lds(lds_dir, cmd):
         f.write("\n".join(lines) + "\n")
     return {"lds_conflict_per_active_cycle": conf / active if active else None,
             "lds_conflict_cycles_per_inst": conf / insts if insts else None}
+
+
+def summarize_counters(pmc_dir, name, title, cmd, per_unit=None, unit=""):
+    """Per-kernel-instance means of an SQ counter pass (rocprofv3 --pmc), with
+    the VALU time they imply (a wavefront VALU instruction takes 4 cycles on
+    a 16-lane SIMD; 1024 SIMDs at 2.4 GHz) and LDS bank conflicts per LDS
+    instruction; per_unit (e.g. windows per dispatch) adds per-unit columns."""
+    rows = _read_csv(_find(pmc_dir, "counter_collection.csv"))
+    per, disp = {}, {}
+    for r in rows:
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hc::", "")
+        if not k.startswith("hc_"):
+            continue
+        per.setdefault(k, {})
+        per[k][r["Counter_Name"]] = per[k].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    lines = [f"# rocprofv3 SQ counters per kernel instance: {title}", "", "Command(s):", "", "```",
+             cmd.strip(), "```", "",
+             "Means per dispatch. VALU time = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz)"
+             + (f"; per {unit}: counter x 64 lanes / {per_unit:.4g} {unit}s per dispatch" if per_unit else "")
+             + ".", "",
+             "| kernel | dispatches | SQ_INSTS_VALU | VALU time (us) | SQ_INSTS_LDS | bank-conflict cycles / LDS instr "
+             "| SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES |" + (f" VALU lane-ops / {unit} | LDS lane-ops / {unit} |" if per_unit else ""),
+             "|---|---|---|---|---|---|---|" + ("---|---|" if per_unit else "")]
+    for k, cs in sorted(per.items()):
+        n = len(disp[k])
+        c = {a: v / n for a, v in cs.items()}
+        valu, lds = c.get("SQ_INSTS_VALU", 0.0), c.get("SQ_INSTS_LDS", 0.0)
+        line = (f"| `{k}` | {n} | {valu:.4g} | {valu * 4 / 1024 / 2.4e3:.1f} | {lds:.4g} | "
+                f"{c.get('SQ_LDS_BANK_CONFLICT', 0.0) / max(lds, 1.0):.2f} | "
+                f"{c.get('SQ_WAIT_INST_LDS', 0.0) / max(c.get('SQ_WAVE_CYCLES', 1.0), 1.0):.3f} |")
+        if per_unit:
+            line += f" {valu * 64 / per_unit:.2f} | {lds * 64 / per_unit:.3f} |"
+        lines.append(line)
+    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
@@ -613,6 +654,9 @@ def main():
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats, args.summary_cmd)
         return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.summary_cmd, args.per_unit, args.unit)
+        return
     if args.summarize:
         summarize(*args.summarize, args.summary_cmd)
         if args.lds_dir:
@@ -751,7 +795,11 @@ def main():
     text_bytes = sum(int(texts[s].size) for (s, _, _, _) in pats)
     value = text_bytes / (ms_step * 1e-3) / 1e9
     launch_ms = per_launch.mean(axis=0)                      # per pattern, mean over steps
-    avg_launch_ms = float(launch_ms.mean())
+    # average call duration over the timed back-to-back steps (one event pair
+    # around all of them on the launch stream); the per-call events of the
+    # second run add about 2 us per call and only serve the per-cell detail
+    avg_launch_ms = ms_step / len(pats)
+    avg_launch_ms_events = float(launch_ms.mean())
     # algorithmic bytes per launch: the text once, the positions written,
     # F and x read
     infos = [B.hc_pattern_info(h) for h in handles]
@@ -794,6 +842,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "hc_search_kernel + hc_emit_kernel (one search call)",
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2),
+                "avg_launch_us_with_call_events": round(avg_launch_ms_events * 1e3, 2),
                 "alg_bytes_per_launch": round(float(alg_bytes.mean())),
                 "frac_text": round(achieved / HBM_PEAK_GBPS, 4),
                 "achieved_method": round(achieved_method, 1) if achieved_method else None,
