@@ -89,7 +89,9 @@ enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENS
  *             only the cache lines that hold them are fetched; long chain
  *             walks and verifications are shared by a whole wavefront.
  *             Tiles hold 256 * segment window starts (segment 0 = 1024, up
- *             to 4096).
+ *             to 4096), the segment rounded to a whole number of shifts
+ *             (m - q + 1) when the shift is 32..4096 starts; one tile per
+ *             workgroup unless wg_per_cu caps the grid.
  * The sentinel variant ignores the schedule (one range per lane). */
 enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIANT_SPARSE = 3 };
 
@@ -116,7 +118,8 @@ typedef struct hc_pattern hc_pattern;   /* opaque; immutable once built      */
  * last tuning of a bucket wins, process-wide. Candidates: q in [1, min(m,
  * 8)], (alpha, w) in {(8,8), (10,16), (11,16), (12,16), (12,32)}, the segment
  * and dense schedules, segments {48, 64, 80, 100}, and for m >= 256 the
- * sparse variant with segments {512, 1024, 2048, 4096}; timed with `patterns`
+ * sparse variant with segments of 1, 2, 4 or 8 shifts (m - q + 1, at most
+ * 4096 starts); timed with `patterns`
  * (1..64) patterns copied from the text at fixed pseudo-random offsets.
  * out[i] (may be NULL) receives the choice for ms[i] and its median text
  * GB/s. Runs on `stream` and synchronises it; allocates a scratch output of

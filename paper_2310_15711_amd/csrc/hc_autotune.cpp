@@ -96,6 +96,12 @@ hc_status time_candidate(const Cand &c, const std::vector<std::vector<uint8_t>> 
     return HC_OK;
 }
 
+// Lane segment of the sparse variant: k shifts of m - q + 1 starts, at most
+// 4096 starts.
+int sparse_segment(int64_t m, int q, int k) {
+    return int(std::min<int64_t>(int64_t(k) * (m - q + 1), 4096));
+}
+
 std::vector<Cand> candidates(int64_t m) {
     static const int shapes[][2] = {{8, 8}, {10, 16}, {11, 16}, {12, 16}, {12, 32}};
     std::vector<Cand> out;
@@ -107,8 +113,11 @@ std::vector<Cand> candidates(int64_t m) {
                 out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_DENSE, 100});
             // long patterns: text read in place (most cache lines never fetched)
             if (m >= 256 && q >= 3)
-                out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, 1024, HC_VARIANT_SPARSE});
+                out.push_back(Cand{q, aw[0], aw[1], HC_SCHED_SEGMENT, sparse_segment(m, q, 1), HC_VARIANT_SPARSE});
         }
+    // m = q = 2 with alpha = 16: the hash is one-to-one on windows (the dense
+    // test needs no comparison with x, and no table in LDS)
+    if (m == 2) out.push_back(Cand{2, 16, 8, HC_SCHED_DENSE, 100});
     return out;
 }
 
@@ -161,11 +170,11 @@ extern "C" hc_status hc_autotune(const uint8_t *d_y, int64_t n, const int64_t *m
         Cand best{0, 0, 0, 0, 0, HC_VARIANT_HC};
         best.ms = 1e30;
         static const int hc_segs[4] = {48, 64, 80, 100};   // larger tiles do not fit the staging
-        static const int sparse_segs[4] = {512, 1024, 2048, 4096};   // the sparse tiles are larger
         for (size_t k = 0; k < std::min<size_t>(4, cs.size()) && st == HC_OK; ++k)
             for (int j = 0; j < 4; ++j) {
                 Cand c = cs[k];
-                c.segment = c.variant == HC_VARIANT_SPARSE ? sparse_segs[j] : hc_segs[j];
+                // sparse lanes take 1, 2, 4 or 8 whole shifts (at most 4096 starts)
+                c.segment = c.variant == HC_VARIANT_SPARSE ? sparse_segment(m, c.q, 1 << j) : hc_segs[j];
                 st = time_candidate(c, pats, np, d_y, n, d_out, cap, d_count, fl, s, &c.ms);
                 if (st != HC_OK) break;
                 if (c.ms < best.ms) best = c;

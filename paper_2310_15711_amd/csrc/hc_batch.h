@@ -16,6 +16,7 @@ struct BPat {            // one pattern of the batch, as the kernel reads it
     uint32_t m, q, s, mask, hv;
     uint32_t x_off;      // byte offset of x in the packed patterns (16-aligned)
     uint32_t pad0, pad1;
+    uint32_t w[4];       // byte weights of the hash (byte_weights: wl0, wl1, wh0, wh1)
 };
 
 struct BItem {           // one work item

@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                 continue;
             }
             const uint32_t S = uint32_t(min<uint64_t>(A.tile, starts - tile_lo));
-            const PatternView P{bp.m, bp.q, bp.s, bp.mask, bp.hv};
+            const PatternView P{bp.m, bp.q, bp.s, bp.mask, bp.hv, bp.w[0], bp.w[1], bp.w[2], bp.w[3]};
             const uint32_t shift = bp.m - bp.q + 1u;
             const TileResult R =
                 bp.m < 2u * bp.q
@@ -527,7 +527,8 @@ hc_status pack_one(const uint8_t *x, int64_t m, int q_req, int alpha, int w, uin
     if (packed.size() > table_bytes) return HC_EINVAL;
     std::memset(F_out, 0, table_bytes);
     std::memcpy(F_out, packed.data(), packed.size());
-    bp = BPat{uint32_t(m), uint32_t(q), uint32_t(pd.s), pd.mask, pd.hv, 0, 0, 0};
+    bp = BPat{uint32_t(m), uint32_t(q), uint32_t(pd.s), pd.mask, pd.hv, 0, 0, 0, {}};
+    byte_weights(bp.q, bp.s, bp.w);
     return HC_OK;
 }
 
@@ -542,7 +543,8 @@ hc_status pack_desc(const uint8_t *x, int64_t m, int q_req, int alpha, int w, BP
     const uint8_t *u = x + (m - q) % q;
     uint32_t v = 0;
     for (int k = q - 1; k >= 0; --k) v = (v << s) + u[k];
-    bp = BPat{uint32_t(m), uint32_t(q), s, mask, v & mask, 0, 0, 0};
+    bp = BPat{uint32_t(m), uint32_t(q), s, mask, v & mask, 0, 0, 0, {}};
+    byte_weights(bp.q, bp.s, bp.w);
     return HC_OK;
 }
 

@@ -34,6 +34,10 @@ const DeviceInfo &device_info();
 // keep their bitmap.
 constexpr uint32_t kSlot = 128;
 
+// Range totals of the ordered output per call (its emit grid is at most this
+// many workgroups when they are used).
+constexpr uint32_t kRsumCap = 2048;
+
 struct Workspace {
     std::mutex mu;                // held by the call that enqueues on this stream
     uint32_t *counts = nullptr;   // tiles_cap entries
@@ -41,6 +45,11 @@ struct Workspace {
     uint32_t *spill = nullptr;    // spill_words_cap entries
     uint32_t tiles_cap = 0;
     uint64_t spill_words_cap = 0;
+    // two arrays of kRsumCap range totals of the ordered output, used by
+    // turns: the current call adds into array `parity` and its emit kernel
+    // clears the other one for the next call (allocated cleared)
+    uint32_t *rsum = nullptr;
+    int parity = 0;
 };
 
 // Workspace of (current device, stream) with room for `tiles` tiles of `tile`
@@ -48,11 +57,16 @@ struct Workspace {
 hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Workspace **out,
                         std::unique_lock<std::mutex> *lock);
 
-// Per-tile results of one search call (counts, slot lists, spilled bitmaps).
+// Per-tile results of one search call (counts, range totals of the ordered
+// output and the ones the emit kernel clears for the next call, or null,
+// slot lists, spilled bitmaps).
 struct TileScratch {
     uint32_t *counts = nullptr;
+    uint32_t *rsum = nullptr;
+    uint32_t *rsum_next = nullptr;
     uint32_t *slots = nullptr;
     uint32_t *spill = nullptr;
+    int *parity = nullptr;   // the workspace's turn, flipped once the call is enqueued
 };
 
 // Device copies of a pattern's F (packed w-bit words) and x on the current

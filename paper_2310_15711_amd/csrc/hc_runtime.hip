@@ -51,6 +51,18 @@ hc_status workspace_for(hipStream_t stream, uint32_t tiles, uint32_t tile, Works
         ws = slot.get();   // entries are never removed: the address stays valid
     }
     std::unique_lock<std::mutex> held(ws->mu);
+    if (!ws->rsum) {
+        if (hipMalloc(reinterpret_cast<void **>(&ws->rsum), sizeof(uint32_t) * 2u * kRsumCap) != hipSuccess) {
+            ws->rsum = nullptr;
+            return HC_ENOMEM;
+        }
+        if (hipMemset(ws->rsum, 0, sizeof(uint32_t) * 2u * kRsumCap) != hipSuccess) {
+            (void)hipFree(ws->rsum);
+            ws->rsum = nullptr;
+            return HC_EHIP;
+        }
+        ws->parity = 0;
+    }
     const uint64_t spill_words = uint64_t(tiles) * (tile / 32u);
     if (ws->tiles_cap < tiles || ws->spill_words_cap < spill_words) {
         // earlier launches on this stream may still use the old buffers

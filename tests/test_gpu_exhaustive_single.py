@@ -26,7 +26,8 @@ pytestmark = pytest.mark.gpu
 
 M_MAX, N_MAX = 6, 12
 GRID = ([(q, a, w) for w in (16, 32) for a in (1, 2, 3, 4, 8, 12) for q in range(1, 7)] +
-        [(q, a, w) for w in (8, 64) for a in (2, 8) for q in (1, 3, 6)])
+        [(q, a, w) for w in (8, 64) for a in (2, 8) for q in (1, 3, 6)] +
+        [(q, 16, 8) for q in (1, 2)])   # one-to-one hashes (s >= 8)
 # (label, segment, schedule, variant): every schedule and variant
 LAUNCHES = [
     ("segment-36", 36, B.HC_SCHED_SEGMENT, B.HC_VARIANT_HC),

@@ -7,9 +7,9 @@
 - The 256 MiB order-2 Markov text, tuned inside the test (hc_autotune on that
   text), each length run with the tuple it chose.
 - Every candidate the tuner can choose (q, alpha, w, schedule, segment and,
-  for m >= 256, the sparse variant with its segments) on 12 MiB texts, so
-  that whatever a tuning run picks has been compared with the oracle over
-  hundreds of tiles."""
+  for m >= 256, the sparse variant with 1, 2, 4 or 8 shifts per lane) on
+  12 MiB texts, so that whatever a tuning run picks has been compared with
+  the oracle over hundreds of tiles."""
 import json
 import os
 import sys
@@ -110,9 +110,13 @@ def tuner_candidates(m):
             for sc in scheds:
                 for seg in (48, 64, 80, 100):
                     out.append(((q, a, w), (seg, sc, B.HC_VARIANT_HC, 0)))
-            if m >= 256 and q >= 3:
-                for seg in (512, 1024, 2048, 4096):
+            if m >= 256 and q >= 3:   # 1, 2, 4 or 8 shifts per lane, at most 4096 starts
+                for k in (1, 2, 4, 8):
+                    seg = min(k * (m - q + 1), 4096)
                     out.append(((q, a, w), (seg, B.HC_SCHED_SEGMENT, B.HC_VARIANT_SPARSE, 0)))
+    if m == 2:   # one-to-one hash on the window, no comparison with x
+        for seg in (48, 64, 80, 100):
+            out.append(((2, 16, 8), (seg, B.HC_SCHED_DENSE, B.HC_VARIANT_HC, 0)))
     return out
 
 
