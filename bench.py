@@ -44,6 +44,8 @@ def parse():
                     help="single workload: leave out the batched and served summaries")
     ap.add_argument("--serve-rates", default="1000,3000,10000,30000,100000")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-tune-requests", type=int, default=1000,
+                    help="served workload: sample requests hc_batch_autotune times the batch knobs on")
     ap.add_argument("--serve-threads", type=int, default=4, help="native submitter threads")
     ap.add_argument("--serve-text-mib", type=int, default=128)
     ap.add_argument("--serve-budget-mib", type=int, default=2048)
@@ -52,7 +54,8 @@ def parse():
     ap.add_argument("--batch-texts", type=int, default=64)
     ap.add_argument("--batch-patterns", type=int, default=4096)
     ap.add_argument("--batch-params", default=None, help="q,alpha,w for the batch plan (0 = library choice)")
-    ap.add_argument("--no-batch-tune", action="store_true", help="batched workload: skip hc_batch_autotune")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="batched and served workloads: skip hc_batch_autotune")
     ap.add_argument("--batch-tune-pairs", type=int, default=22000,
                     help="batched workload: pairs sampled by hc_batch_autotune")
     ap.add_argument("--batch-oracle-pairs", type=int, default=1000,
@@ -153,6 +156,22 @@ def _counter_per_dispatch(d, counter, name_part):
     return (sum(per.values()) / len(per)) if per else None, len(per)
 
 
+def _counter_sum(d, counter, name_parts):
+    """Sum of a counter over the dispatches of kernels whose name contains one
+    of name_parts, and the number of those dispatches."""
+    rows = _read_csv(_find(d, "counter_collection.csv"))
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] == counter and any(p in r["Kernel_Name"] for p in name_parts):
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return sum(per.values()), len(per)
+
+
+# the first kernel of a single-pattern search call (streaming or sparse);
+# hc_emit_kernel follows each
+SEARCH_KERNELS = ("hc_search_kernel", "hc_sparse_kernel")
+
+
 def summarize_stats(stats_dir, name, title, cmd):
     """Kernel table of one rocprofv3 --kernel-trace --stats run."""
     stats = _read_csv(_find(stats_dir, "kernel_stats.csv"))
@@ -172,13 +191,13 @@ def summarize_lds(lds_dir, cmd):
     rows = _read_csv(_find(lds_dir, "counter_collection.csv"))
     tot = {}
     for r in rows:
-        if "hc_search_kernel" in r["Kernel_Name"]:
+        if any(p in r["Kernel_Name"] for p in SEARCH_KERNELS):
             tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     conf, active = tot.get("SQ_LDS_BANK_CONFLICT", 0.0), tot.get("SQ_ACTIVE_INST_LDS", 0.0)
     insts = tot.get("SQ_INSTS_LDS", 0.0)
     lines = ["# LDS bank conflicts of the single-pattern search kernels (rocprofv3 --pmc)", "",
              "Command(s):", "", "```", cmd.strip(), "```", "",
-             "| counter (summed over hc_search_kernel dispatches) | value |", "|---|---|"]
+             "| counter (summed over hc_search_kernel and hc_sparse_kernel dispatches) | value |", "|---|---|"]
     lines += [f"| {k} | {v:.0f} |" for k, v in sorted(tot.items())]
     lines += ["", f"- Bank-conflict cycles per cycle of LDS instruction activity "
                   f"(SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS): {conf / active:.3f}" if active else "",
@@ -240,23 +259,26 @@ def summarize(stats_dir, fetch_dir, write_dir, calib_prefix, cmd):
         avg[short] = (int(r["Calls"]), a)
         lines.append(f"| `{short}` | {r['Calls']} | {a:.2f} | {float(r['MinNs'])/1e3:.2f} | "
                      f"{float(r['MaxNs'])/1e3:.2f} | {float(r['Percentage']):.2f}% |")
-    search = [v for k, v in avg.items() if "hc_search_kernel" in k]
+    search = [v for k, v in avg.items() if any(p in k for p in SEARCH_KERNELS)]
     emit = [v for k, v in avg.items() if "hc_emit_kernel" in k]
     if search and emit:
         calls = sum(c for c, _ in search)
         s_avg = sum(c * a for c, a in search) / calls
         e_avg = sum(c * a for c, a in emit) / sum(c for c, _ in emit)
-        lines += ["", f"Search call = `hc_search_kernel` + `hc_emit_kernel`: average {s_avg:.2f} + "
-                      f"{e_avg:.2f} = {s_avg + e_avg:.2f} us per call ({calls} calls)."]
+        lines += ["", f"Search call = `hc_search_kernel` or `hc_sparse_kernel`, then `hc_emit_kernel`: "
+                      f"average {s_avg:.2f} + {e_avg:.2f} = {s_avg + e_avg:.2f} us per call ({calls} calls)."]
     out = os.path.join(ROOT, "profiles", "hc_search_single_pattern_kernel_stats.md")
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     # traffic: HBM bytes per search call, scaled by the copy kernel's counters
-    fetch_s, nf = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "hc_search_kernel")
-    fetch_e, _ = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "hc_emit_kernel")
-    write_s, nw = _counter_per_dispatch(write_dir, "WRITE_SIZE", "hc_search_kernel")
-    write_e, _ = _counter_per_dispatch(write_dir, "WRITE_SIZE", "hc_emit_kernel")
+    # per call: the search (or sparse) kernel and the emit kernel that follows
+    fs, nf = _counter_sum(fetch_dir, "FETCH_SIZE", SEARCH_KERNELS)
+    fe, _ = _counter_sum(fetch_dir, "FETCH_SIZE", ("hc_emit_kernel",))
+    ws, nw = _counter_sum(write_dir, "WRITE_SIZE", SEARCH_KERNELS)
+    we, _ = _counter_sum(write_dir, "WRITE_SIZE", ("hc_emit_kernel",))
+    fetch_s, fetch_e = fs / max(nf, 1), fe / max(nf, 1)
+    write_s, write_e = ws / max(nw, 1), we / max(nw, 1)
     # the copy kernel only (the fills that create the sources read nothing)
     cf, _ = _counter_per_dispatch(calib_prefix + "_fetch", "FETCH_SIZE", "copyBuffer")
     cw, _ = _counter_per_dispatch(calib_prefix + "_write", "WRITE_SIZE", "copyBuffer")
@@ -538,6 +560,26 @@ def run_served(args):
     out = {}
     from oracle import hc_oracle as O
 
+    # the server's batched kernel takes the process-wide batch knobs (table
+    # shape, lane segment, group size, workgroups per CU): tuned once at
+    # start-up on a sample of requests of the same kind (its own seed), as a
+    # deployment would, outside every timed region
+    stune = None
+    if not args.no_batch_tune:
+        t0 = time.time()
+        sreqs = W.request_stream(texts, args.serve_tune_requests / 2.0, 2.0, sub=97)
+        soff = np.zeros(len(texts) + 1, dtype=np.int64)
+        soff[1:] = np.cumsum([t.size for t in texts])
+        d_all = torch.cat(dtexts)
+        stune = B.hc_batch_autotune(d_all, soff, [r.pattern for r in sreqs],
+                                    np.arange(len(sreqs), dtype=np.int32),
+                                    np.array([r.text for r in sreqs], dtype=np.int32),
+                                    max_pairs=len(sreqs))
+        del d_all
+        torch.cuda.empty_cache()
+        stune = {"seconds": round(time.time() - t0, 1), "requests": len(sreqs), "choice": stune}
+        log(f"served batch knobs tuned in {stune['seconds']}s: {stune['choice']}")
+
     o_checked, o_equal, o_bad = 0, 0, []
     start_delay = 0.05
     for ri, rate in enumerate(rates):
@@ -641,7 +683,7 @@ def run_served(args):
     return {"workload": f"served HC: {len(texts)} resident texts x {args.serve_text_mib} MiB "
                         f"(4 iid bytes, 4 order-2 Markov), Poisson arrivals for "
                         f"{args.serve_seconds} s per rate, m log-uniform 4..2048",
-            "budget_mib": args.serve_budget_mib, "rates": out,
+            "budget_mib": args.serve_budget_mib, "batch_tuning": stune, "rates": out,
             "parity": {"checked": o_checked, "equal": o_equal, "exact": o_equal == o_checked,
                        "what": "seeded sample of served requests (spread over the rates), complete "
                                "lists vs the oracle's brute force", "mismatches": o_bad},
@@ -840,7 +882,7 @@ def main():
 
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "hc_search_kernel + hc_emit_kernel (one search call)",
+                "kernel": "hc_search_kernel or hc_sparse_kernel, then hc_emit_kernel (one search call)",
                 "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                 "avg_launch_us_with_call_events": round(avg_launch_ms_events * 1e3, 2),
                 "alg_bytes_per_launch": round(float(alg_bytes.mean())),

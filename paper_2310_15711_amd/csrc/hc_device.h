@@ -176,6 +176,11 @@ struct Parked {
 };
 constexpr uint32_t kParkCap = 32;   // parked walks per workgroup and round
 constexpr int kLocalSteps = 8;      // chain steps a lane takes before parking
+// The same for walks read in place (sparse variant): each step there is a
+// dependent global load, so the walk is handed to the wavefront (64 q-grams
+// per load round) after one; the walk of a true occurrence crosses m / q
+// links and sets the time of its tile.
+constexpr int kSparseLocalSteps = 1;
 
 // Outcome of an attempt: the next window end, or "parked".
 constexpr uint32_t kParkedJ = 0xFFFFFFFFu;
@@ -595,8 +600,8 @@ __device__ __forceinline__ bool span_chain(const uint32_t (&w)[4], const Pattern
 // absolute address of tile position 0) with the 16 bytes ending at J already
 // in w: the first word, then the chain of links towards the window start,
 // its first 16 / Q - 1 steps from w and the rest read in place. Returns the
-// next window end; after kLocalSteps links read in place the walk is handed
-// back (kParkedJ) with its position in (e, v, z). Marks candidates.
+// next window end; after kSparseLocalSteps links read in place the walk is
+// handed back (kParkedJ) with its position in (e, v, z). Marks candidates.
 template <int Q, typename WT>
 __device__ __forceinline__ uint32_t sparse_attempt(const GlobalText &T, uintptr_t base, const WT *__restrict__ F,
                                                    const PatternView &P, uint32_t J, const uint32_t (&w)[4],
@@ -611,7 +616,7 @@ __device__ __forceinline__ uint32_t sparse_attempt(const GlobalText &T, uintptr_
     e = J;
     uint32_t next = 0;
     if (span_chain<Q, 1, KS, WT>(w, P, F, lo, e, v, z, next)) return next;
-    int steps = kLocalSteps;
+    int steps = kSparseLocalSteps;
     while (int32_t(e) >= lo) {
         if (steps-- == 0) return kParkedJ;
         const uint32_t ep = e - Q;

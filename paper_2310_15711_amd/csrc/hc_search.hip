@@ -249,9 +249,10 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
         const uint32_t lo = min(S, tid * A.seg), hi = min(S, lo + A.seg);
         uint32_t J = lo + A.m - 1u;
         const uint32_t Jend = hi + A.m - 1u;   // window ends of this lane: [J, Jend)
-        // A chain walk longer than kLocalSteps links is parked (state in e,
-        // v, z) and finished by the whole wavefront, 64 q-grams per round
-        // trip, instead of one dependent memory access per link.
+        // A chain walk longer than kSparseLocalSteps links past the span is
+        // parked (state in e, v, z) and finished by the whole wavefront, 64
+        // q-grams per round trip, instead of one dependent memory access per
+        // link.
         bool parked = false;
         uint32_t e = 0, v = 0;
         WT z = 0;
@@ -304,8 +305,8 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
         uint32_t total = 0, mine = 0, w0 = 0, w1 = 0;
         if (has) {
             // verification, one candidate at a time per wavefront: the 64
-            // lanes compare 64 dwords of the window at once (loads in flight
-            // together instead of one dependent load per dword)
+            // lanes compare 256 dwords of the window per round, all their
+            // loads in flight together
             const uint32_t words = (S + 31u) / 32u;
             const uint32_t wid = tid / kWave, nw = (A.m + 3u) >> 2;
             const uint32_t tail = (A.m & 3u) ? ((1u << (8u * (A.m & 3u))) - 1u) : 0xFFFFFFFFu;
@@ -324,12 +325,22 @@ __global__ __launch_bounds__(kBlock) void hc_sparse_kernel(SearchArgs A) {
                         const uint32_t sh = uint32_t(wa & 3u);
                         const uintptr_t wb = wa & ~uintptr_t(3);
                         bool diff = false;
-                        for (uint32_t k = lane; k < nw; k += kWave) {
-                            const uint32_t word = __builtin_amdgcn_alignbyte(gdword(T, wb + 4u * (k + 1u)),
-                                                                             gdword(T, wb + 4u * k), sh);
-                            uint32_t d = word ^ x32[k];
-                            if (k + 1u == nw) d &= tail;
-                            diff |= d != 0u;
+                        constexpr int kV = 4;   // dwords per lane per round
+                        for (uint32_t k0 = 0; k0 < nw; k0 += kV * kWave) {
+                            uint32_t dl[kV], dh[kV];
+#pragma unroll
+                            for (int u = 0; u < kV; ++u) {
+                                const uint32_t k = k0 + uint32_t(u) * kWave + lane;
+                                dl[u] = k < nw ? gdword(T, wb + 4u * k) : 0u;
+                                dh[u] = k < nw ? gdword(T, wb + 4u * (k + 1u)) : 0u;
+                            }
+#pragma unroll
+                            for (int u = 0; u < kV; ++u) {
+                                const uint32_t k = k0 + uint32_t(u) * kWave + lane;
+                                uint32_t d = __builtin_amdgcn_alignbyte(dh[u], dl[u], sh) ^ (k < nw ? x32[k] : 0u);
+                                if (k + 1u == nw) d &= tail;
+                                diff |= k < nw && d != 0u;
+                            }
                         }
                         if (__ballot(diff) != 0ull) keep &= ~(1u << bit);
                     }
