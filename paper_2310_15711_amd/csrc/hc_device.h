@@ -420,9 +420,12 @@ __device__ __forceinline__ void hc_wave(const uint32_t *__restrict__ t32, uint32
 // them a wavefront per SIMD, worth more than larger tiles.
 constexpr int kStageMax = 7;
 
-// Dense-schedule kernels hold five (tiles up to 20 K starts): they are the
-// most VALU-bound and gain most from the extra wavefronts.
+// Dense-schedule kernels with q >= 3 hold five (tiles up to 20 K starts):
+// they are the most VALU-bound and gain most from the extra wavefronts; with
+// q <= 2 their loop is short enough that seven (larger tiles) measured 5-10 %
+// faster, and 1 % slower at q = 3.
 constexpr int kStageDense = 5;
+__host__ __device__ constexpr int dense_chunks(int q) { return q <= 2 ? kStageMax : kStageDense; }
 
 template <int N = kStageMax>
 struct Stage {
@@ -840,10 +843,13 @@ __device__ __forceinline__ TileResult shc_tile(const uint32_t *__restrict__ t32,
 // No links (m < 2q): 16 windows per lane and step. The 16 window-end hashes
 // are formed two at a time in 16-bit lanes: column k holds byte k of every
 // window's q-gram, zero-extended in pairs, and is added times 2^(s k); sums
-// wrap mod 2^16, which 2^alpha divides (alpha <= 16). WIDE: alpha = 16 (no
-// spare top bit in a lane for the add-based zero test). The marks left are
-// occurrences (every candidate has been compared with x).
-template <int Q, bool WIDE>
+// wrap mod 2^16, which 2^alpha divides (alpha <= 16). S8: q = 2 and s = 8
+// (alpha = 16), where the hash is the window's own 16-bit value, gathered
+// by one permute per pair. t = (H xor H_v) mod 2^alpha per half; the 16
+// halves are folded by packed 16-bit minimums, so one test per step tells
+// whether any window passed, and only such steps take the bits one by one.
+// The marks left are occurrences (every candidate has been compared with x).
+template <int Q, bool S8>
 __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t32, uint32_t tb,
                                                   const uint32_t *__restrict__ x32, const PatternView &P,
                                                   uint32_t S, uint32_t *bm) {
@@ -873,36 +879,61 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
         // pair i = windows 2i (low half) and 2i + 1 (high half); byte k of
         // their q-grams sits at p0 + c and p0 + c + 1, c = PRE + 1 - Q + k + 2i
         u16x2 acc[8];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const uint32_t mk = 1u << (P.s * uint32_t(k));   // s k <= alpha - s < 16
+        if constexpr (S8) {
+            static_assert(Q == 2, "one-to-one 16-bit windows");
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                // v_perm numbers the bytes of {src0, src1} from src1's lowest;
-                // selector 0x0C yields a zero byte
-                const int c = PRE + 1 - Q + k + 2 * i;
+                // bytes c, c + 1 (low half) and c + 1, c + 2 (high half)
+                const int c = PRE - 1 + 2 * i;
                 const int h = (c >> 2) < NWW - 2 ? (c >> 2) : NWW - 2;
                 const uint32_t o = uint32_t(c - 4 * h);
-                const uint32_t pr = __builtin_amdgcn_perm(w[h + 1], w[h], 0x0C000C00u | o | ((o + 1u) << 16));
-                const u16x2 r = __builtin_bit_cast(u16x2, pr);
-                acc[i] = k == 0 ? r : acc[i] + r * u16x2{uint16_t(mk), uint16_t(mk)};
+                acc[i] = __builtin_bit_cast(
+                    u16x2, __builtin_amdgcn_perm(w[h + 1], w[h], o | ((o + 1u) << 8) | ((o + 1u) << 16) | ((o + 2u) << 24)));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const uint32_t mk = 1u << (P.s * uint32_t(k));   // s k <= alpha - s < 16
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    // v_perm numbers the bytes of {src0, src1} from src1's lowest;
+                    // selector 0x0C yields a zero byte
+                    const int c = PRE + 1 - Q + k + 2 * i;
+                    const int h = (c >> 2) < NWW - 2 ? (c >> 2) : NWW - 2;
+                    const uint32_t o = uint32_t(c - 4 * h);
+                    const uint32_t pr = __builtin_amdgcn_perm(w[h + 1], w[h], 0x0C000C00u | o | ((o + 1u) << 16));
+                    const u16x2 r = __builtin_bit_cast(u16x2, pr);
+                    acc[i] = k == 0 ? r : acc[i] + r * u16x2{uint16_t(mk), uint16_t(mk)};
+                }
             }
         }
-        // per half t = (H ^ H_v) mod 2^alpha; bit 15 of nz is set iff t != 0
-        // (alpha <= 15: t + 0x7FFF cannot carry out of the half)
-        uint32_t nz[8], all = 0x80008000u;
+        // per half t = (H ^ H_v) mod 2^alpha: zero exactly when the window passes
+        uint32_t t[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const uint32_t t = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
-            nz[i] = WIDE ? (((t & 0x7FFF7FFFu) + 0x7FFF7FFFu) | t) : (t + 0x7FFF7FFFu);
-            all &= nz[i];
-        }
+        for (int i = 0; i < 8; ++i) t[i] = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
+        u16x2 mn = __builtin_bit_cast(u16x2, t[0]);
+#pragma unroll
+        for (int i = 1; i < 8; ++i) mn = __builtin_elementwise_min(mn, __builtin_bit_cast(u16x2, t[i]));
+        const uint32_t mv = __builtin_bit_cast(uint32_t, mn);
+        // a zero half: some window passed (exact for 16-bit halves)
+        const bool hit = ((mv - 0x00010001u) & ~mv & 0x80008000u) != 0u;
         uint32_t bits = 0;
-        if (all != 0x80008000u) {   // some window-end hash equals H_v
-            uint32_t e = 0;
+        if (__builtin_amdgcn_ballot_w64(hit) != 0ull) {   // uniform: rare unless windows match often
+            // nz: 1 in a half iff that half of t is non-zero (a packed
+            // minimum with 1, written out so that it stays one instruction
+            // and is not computed above the branch); the bytes 0 and 2 of
+            // two pairs are gathered into one dword and weighted 1, 2, 4, 8
+            uint32_t nz[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) e |= (~nz[i] & 0x80008000u) >> (15 - 2 * i);
-            bits = (e | (e >> 15)) & 0xFFFFu;
+            for (int i = 0; i < 8; ++i)   // both halves of the second operand: 0x0001 0x0001
+                asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(nz[i]) : "v"(t[i]), "s"(0x00010001u));
+            uint32_t nb = 0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t four = __builtin_amdgcn_perm(nz[2 * p + 1], nz[2 * p], 0x06040200u);
+                nb |= __builtin_amdgcn_udot4(four, 0x08040201u, 0u, false) << (4 * p);
+            }
+            bits = nb ^ 0xFFFFu;                                  // window j passed: bit j
             if (st0 + 16u > S) bits &= (1u << (S - st0)) - 1u;   // windows past the tile
         }
         if (bits) {
@@ -990,8 +1021,13 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
                                                  uint32_t &it) {
     bool found;
     if constexpr (C == 0)
-        found = P.mask > 0x7FFFu ? dense_mark_nolink<Q, true>(t32, tb, x32, P, S, bm)
-                                 : dense_mark_nolink<Q, false>(t32, tb, x32, P, S, bm);
+    {
+        if constexpr (Q == 2)
+            found = P.s == 8u ? dense_mark_nolink<2, true>(t32, tb, x32, P, S, bm)
+                              : dense_mark_nolink<2, false>(t32, tb, x32, P, S, bm);
+        else
+            found = dense_mark_nolink<Q, false>(t32, tb, x32, P, S, bm);
+    }
     else
         found = dense_mark<Q, WT, C>(t32, tb, F, x32, P, S, bm);
     if (found) misc[8 + (it & 1u)] = 1u;

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void hc_search_kernel(SearchArgs A) {
     // ---- search phase: workgroup b takes tiles b, b + G, b + 2G, ... (at
     // any moment the grid reads one contiguous stretch of the text)
     constexpr bool kDense = SCHED >= HC_SCHED_DENSE && SCHED < kSchedShc;
-    Stage<kDense ? kStageDense : kStageMax> stage;
+    Stage<kDense ? dense_chunks(Q) : kStageMax> stage;
     const uint32_t G = gridDim.x;
     uint32_t tb = 0;
     if (blockIdx.x < A.n_tiles) {
@@ -852,7 +852,7 @@ hc_status launch_single(const hc_pattern *p, const DeviceCopy &dc, const uint8_t
         const int links = int(m) / pd.q - 1;
         sched = (links == 0 || (pd.q <= 4 && links <= 3)) ? HC_SCHED_DENSE + links : HC_SCHED_SEGMENT;
     }
-    const int chunks = sched >= HC_SCHED_DENSE && sched < kSchedShc ? kStageDense : kStageMax;
+    const int chunks = sched >= HC_SCHED_DENSE && sched < kSchedShc ? dense_chunks(pd.q) : kStageMax;
     while (kBlock * seg + m - 1u > stage_limit(kBlock, chunks) && seg > 8) seg -= 4;
     if (L.total > di.max_lds_per_block || kBlock * seg + m - 1u > stage_limit(kBlock, chunks)) return HC_EINVAL;
     L = lds_layout(kBlock * seg, m, table_bytes, extra);
