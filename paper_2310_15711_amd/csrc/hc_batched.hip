@@ -363,6 +363,27 @@ __global__ __launch_bounds__(256) void hc_scan_apply(const uint64_t *in, uint64_
 
 __global__ void hc_scan_total(const uint64_t *grand, int64_t *out_last) { *out_last = int64_t(*grand); }
 
+// The same scan in one launch when one block holds every value (n <=
+// kScanBlock): the exclusive prefix of each value and, after them, the total.
+__global__ __launch_bounds__(256) void hc_scan_single(const uint64_t *in, uint64_t n, int64_t *out) {
+    __shared__ uint64_t lds8[4];
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+    for (uint32_t k = 0; k < kScanItems; ++k) {
+        const uint64_t i = uint64_t(threadIdx.x) * kScanItems + k;
+        v[k] = i < n ? in[i] : 0ull;
+        s += v[k];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl64(s, lds8, &tot);
+    for (uint32_t k = 0; k < kScanItems; ++k) {
+        const uint64_t i = uint64_t(threadIdx.x) * kScanItems + k;
+        if (i < n) out[i] = int64_t(run);
+        run += v[k];
+    }
+    if (threadIdx.x == 0) out[n] = int64_t(tot);
+}
+
 // Copies each pair's positions into place: one wavefront per pair walks the
 // pair's tiles in order (64 at a time, prefix within the pair by a scan).
 // Does nothing when the search ran out of scratch (ctl[2] set): some entries
@@ -710,18 +731,22 @@ hc_status batch_enqueue(BatchDev &D, int64_t *d_pos, int64_t cap, int64_t *d_pai
             hipLaunchKernelGGL(hc_batch_kernel<uint32_t>, dim3(D.grid), dim3(kThreads), D.lds, s, A);
     }
     const uint32_t pgrid = uint32_t((uint64_t(D.n_pairs) * kWave + 255u) / 256u);
-    if (D.n_pairs > 0) {
+    if (D.n_pairs > 0)
         hipLaunchKernelGGL(hc_pair_totals, dim3(pgrid), dim3(256), 0, s, D.pair_base.as<uint64_t>(),
                            uint64_t(D.n_pairs), D.counts.as<uint32_t>(), D.tot.as<uint64_t>());
+    if (uint64_t(D.n_pairs) <= kScanBlock) {
+        // one block holds every total: one launch instead of four
+        hipLaunchKernelGGL(hc_scan_single, dim3(1), dim3(256), 0, s, D.tot.as<uint64_t>(), uint64_t(D.n_pairs),
+                           d_pair_off);
+    } else {
         hipLaunchKernelGGL(hc_scan_reduce, dim3(D.nb), dim3(256), 0, s, D.tot.as<uint64_t>(),
                            uint64_t(D.n_pairs), D.bsum.as<uint64_t>());
-    }
-    hipLaunchKernelGGL(hc_scan_blocks, dim3(1), dim3(256), 0, s, D.bsum.as<uint64_t>(), D.nb,
-                       D.grand.as<uint64_t>());
-    if (D.n_pairs > 0)
+        hipLaunchKernelGGL(hc_scan_blocks, dim3(1), dim3(256), 0, s, D.bsum.as<uint64_t>(), D.nb,
+                           D.grand.as<uint64_t>());
         hipLaunchKernelGGL(hc_scan_apply, dim3(D.nb), dim3(256), 0, s, D.tot.as<uint64_t>(), uint64_t(D.n_pairs),
                            D.bsum.as<uint64_t>(), d_pair_off);
-    hipLaunchKernelGGL(hc_scan_total, dim3(1), dim3(1), 0, s, D.grand.as<uint64_t>(), d_pair_off + D.n_pairs);
+        hipLaunchKernelGGL(hc_scan_total, dim3(1), dim3(1), 0, s, D.grand.as<uint64_t>(), d_pair_off + D.n_pairs);
+    }
     if (D.n_pairs > 0 && cap > 0)
         hipLaunchKernelGGL(hc_pair_emit, dim3(pgrid), dim3(256), 0, s, D.pair_base.as<uint64_t>(),
                            uint64_t(D.n_pairs), D.counts.as<uint32_t>(), D.toff.as<uint32_t>(),
