@@ -745,8 +745,12 @@ def main():
             texts[s] = W.single_text(s, n)
         per = {(s, m): W.single_patterns(texts[s], s, m, args.per_length) for s in sigmas for m in lengths}
         # consecutive launches go to different texts (3 x 256 MiB do not fit
-        # in the 256 MB Infinity Cache), so every launch reads its text from HBM
-        pats = [(s, m) + per[(s, m)][j] for m in lengths for j in range(args.per_length) for s in sigmas]
+        # in the 256 MB Infinity Cache) and to different cells: the launches
+        # of one cell are 29 launches apart, most of them streaming a whole
+        # text, so a launch that reads only part of its text (the sparse
+        # variant touches the same lines for every pattern of one length)
+        # does not find them in the cache from the cell's previous launch
+        pats = [(s, m) + per[(s, m)][j] for j in range(args.per_length) for m in lengths for s in sigmas]
         workload = (f"single-pattern HC: {len(sigmas)} iid texts x {args.text_mib} MiB "
                     f"(sigma {args.sigmas}), m in {lengths}, {args.per_length} patterns each")
     elif args.workload == "markov":
