@@ -691,6 +691,70 @@ def run_served(args):
             "speedup_vs_per_request_gpu_busy": round(best["agg_gbps"] / baseline["gbps_gpu_busy"], 2)}
 
 
+def time_cpu_hc(pats, infos, texts, threads):
+    """The paper's sequential HC on the host: the oracle's C scan (its own
+    preprocessing, then the searching phase over the whole text, with the
+    line accounting the method-byte table uses), one pattern per (sigma, m)
+    cell with that cell's tuned (q, alpha, w); on one core, and the same
+    patterns spread over all cores; preprocessing alone timed on an empty
+    text."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import hc_oracle as O
+
+    first = {}
+    for i, (s, m, _, _) in enumerate(pats):
+        first.setdefault((s, m), i)
+    jobs = [(pats[i][3], texts[pats[i][0]], infos[i]) for i in first.values()]
+
+    def one(j, y=None):
+        x, yy, inf = j
+        return O.hc_scan(x, yy if y is None else y, inf["q"], inf["alpha"], inf["w"])
+
+    nbytes = float(sum(y.size for _, y, _ in jobs))
+    t0 = time.perf_counter()
+    for j in jobs:
+        one(j)
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, jobs))
+    t_all = time.perf_counter() - t0
+    empty = np.zeros(0, dtype=np.uint8)
+    t0 = time.perf_counter()
+    for j in jobs:
+        one(j, empty)
+    t_pre = time.perf_counter() - t0
+    return {"one_core_gbps": round(nbytes / t_one / 1e9, 3),
+            "one_core_search_only_gbps": round(nbytes / max(t_one - t_pre, 1e-9) / 1e9, 3),
+            "all_cores_gbps": round(nbytes / t_all / 1e9, 3), "cores": threads,
+            "preprocessing_ms_per_pattern": round(t_pre / len(jobs) * 1e3, 3),
+            "kind": "oracle (sequential HC, hc_seq.c)",
+            "sample": f"{len(jobs)} patterns (one per sigma and m, the cell's tuned q, alpha, w), each over "
+                      f"its full text"}
+
+
+def run_markov_leg(args):
+    """The order-2 Markov workload (three 256 MiB walks over 27 symbols, m
+    4..1024) in a child process of its own (it tunes its own texts), reduced
+    to its value, parity and roofline."""
+    import subprocess
+
+    # the oracle leg runs on 4 patterns per cell: its lists are the parity check
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "markov", "--no-extras",
+           "--cpu-sample-patterns", "4", "--steps", str(args.steps), "--warmup", str(args.warmup),
+           "--per-length", str(min(args.per_length, 50))]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"markov leg failed ({r.returncode}): {r.stderr[-2000:]}")
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    log(f"markov leg: {d['value']} GB/s, parity {d['parity']['equal']}/{d['parity']['checked']}")
+    return {"value": d["value"], "unit": d["unit"], "ms_per_step": d["ms_per_step"],
+            "config": {"workload": d["config"]["workload"]}, "parity": d["parity"],
+            "roofline": {k: d["roofline"][k] for k in ("achieved", "frac", "avg_launch_us", "frac_method")},
+            "detail_median_text_gbps": d["detail_median_text_gbps"]}
+
+
 def main():
     args = parse()
     if args.summarize_stats:
@@ -755,10 +819,14 @@ def main():
                     f"(sigma {args.sigmas}), m in {lengths}, {args.per_length} patterns each")
     elif args.workload == "markov":
         lengths = [int(v) for v in args.lengths.split(",")] if args.lengths else list(W.MARKOV_LENGTHS)
-        texts[27] = W.markov_text(n)
-        pats = [(27, m, off, x) for m in lengths
-                for off, x in W.markov_patterns(texts[27], m, args.per_length)]
-        workload = (f"single-pattern HC on order-2 Markov text ({args.text_mib} MiB, 27 symbols), "
+        # three walks of the same chain (keys 27, 28, 29), launches
+        # alternating between them and between cells as in the iid workload
+        walks = (27, 28, 29)
+        for k, key in enumerate(walks):
+            texts[key] = W.markov_text(n, walk_sub=k)
+        per = {(key, m): W.markov_patterns(texts[key], m, args.per_length) for key in walks for m in lengths}
+        pats = [(key, m) + per[(key, m)][j] for j in range(args.per_length) for m in lengths for key in walks]
+        workload = (f"single-pattern HC on order-2 Markov text (3 walks x {args.text_mib} MiB, 27 symbols), "
                     f"m in {lengths}, {args.per_length} patterns each")
     else:
         p = W.planted_config()
@@ -868,6 +936,7 @@ def main():
     for i, (s, m, _, _) in enumerate(pats):
         detail.setdefault(f"{s}/{m}", []).append(texts[s].size / (launch_ms[i] * 1e-3) / 1e9)
         cells.setdefault((s, m), []).append(i)
+    spread = {k: [round(float(np.percentile(v, q)), 1) for q in (10, 50, 90)] for k, v in detail.items()}
     detail = {k: round(float(np.median(v)), 1) for k, v in detail.items()}
     if args.detail:
         for k, v in detail.items():
@@ -899,6 +968,7 @@ def main():
 
     cpu = None
     parity = None
+    cpu_hc = None
     if not args.no_cpu_baseline:
         from oracle import hc_oracle as O
 
@@ -921,6 +991,8 @@ def main():
                "sample": f"{len(sample)} patterns ({args.cpu_sample_patterns} per sigma and m), each "
                          f"over its full {args.text_mib} MiB text, {dt:.1f} s"}
         parity = check_single(pats, sample, wants, cnt, handles, launches, dtexts, stream)
+        if args.workload == "single":
+            cpu_hc = time_cpu_hc(pats, infos, texts, th)
 
     rec = {
         "metric": "text GB/s per pattern (HC vs batched) + % HBM peak; p50/p99 search latency",
@@ -949,7 +1021,10 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "detail_median_text_gbps": detail,
+        "detail_p10_p50_p90_text_gbps": spread,
     }
+    if cpu_hc is not None:
+        rec["cpu_hc"] = cpu_hc
     if args.workload == "single" and not args.no_extras:
         del dtexts, out
         torch.cuda.empty_cache()
@@ -960,6 +1035,7 @@ def main():
                           "speedup_vs_per_pattern_gpu_busy": bt["speedup_vs_per_pattern_gpu_busy"]}
         B.hc_autotune_reset()   # the served leg runs on the library's defaults
         rec["served"] = run_served(args)
+        rec["markov"] = run_markov_leg(args)
     print(json.dumps(rec), flush=True)
 
 
