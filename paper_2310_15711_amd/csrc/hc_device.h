@@ -848,8 +848,15 @@ __device__ __forceinline__ TileResult shc_tile(const uint32_t *__restrict__ t32,
 // by one permute per pair. t = (H xor H_v) mod 2^alpha per half; the 16
 // halves are folded by packed 16-bit minimums, so one test per step tells
 // whether any window passed, and only such steps take the bits one by one.
+// SAD4: m = 4 (q = 3 or 4). A window is one dword, so the filter and the
+// verification both look at the same 4 bytes: the window is compared with x
+// directly, t = the sum of absolute byte differences, zero exactly for an
+// occurrence; one quad-SAD instruction gives it for four consecutive
+// windows (the four byte offsets of an 8-byte source) as four 16-bit halves.
 // The marks left are occurrences (every candidate has been compared with x).
-template <int Q, bool S8>
+constexpr int kNolinkHash = 0, kNolinkS8 = 1, kNolinkSad4 = 2;
+
+template <int Q, int MODE>
 __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t32, uint32_t tb,
                                                   const uint32_t *__restrict__ x32, const PatternView &P,
                                                   uint32_t S, uint32_t *bm) {
@@ -863,7 +870,8 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
     const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
     // q = m and s >= 8: the hash is one-to-one on windows (each byte in its
     // own 8 bits), so a window passes the test exactly when it equals x
-    const bool exact = P.m == uint32_t(Q) && P.s >= 8u;
+    const bool exact = MODE == kNolinkSad4 || (P.m == uint32_t(Q) && P.s >= 8u);
+    const uint32_t x4 = x32[0];   // SAD4: the pattern's 4 bytes
     uint32_t cmask = 0;   // this lane's steps with candidates
     uint32_t ks = 0;
     for (uint32_t g = threadIdx.x; g < steps; g += kThreads, ++ks) {
@@ -876,41 +884,57 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
         for (int i = 0; i <= NWW; ++i) d[i] = t32[base + i];
 #pragma unroll
         for (int i = 0; i < NWW; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
-        // pair i = windows 2i (low half) and 2i + 1 (high half); byte k of
-        // their q-grams sits at p0 + c and p0 + c + 1, c = PRE + 1 - Q + k + 2i
-        u16x2 acc[8];
-        if constexpr (S8) {
-            static_assert(Q == 2, "one-to-one 16-bit windows");
+        // pair i = windows 2i (low half) and 2i + 1 (high half); per half
+        // t = 0 exactly when the window passes
+        uint32_t t[8];
+        if constexpr (MODE == kNolinkSad4) {
+            static_assert(Q >= 3 && Q <= 4, "m = 4 without links");
+            // window 4h + k starts at byte 4h + k of the words (p0 is the
+            // first window's start)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                // bytes c, c + 1 (low half) and c + 1, c + 2 (high half)
-                const int c = PRE - 1 + 2 * i;
-                const int h = (c >> 2) < NWW - 2 ? (c >> 2) : NWW - 2;
-                const uint32_t o = uint32_t(c - 4 * h);
-                acc[i] = __builtin_bit_cast(
-                    u16x2, __builtin_amdgcn_perm(w[h + 1], w[h], o | ((o + 1u) << 8) | ((o + 1u) << 16) | ((o + 2u) << 24)));
+            for (int h = 0; h < 4; ++h) {
+                const uint64_t src = (uint64_t(w[h + 1]) << 32) | w[h];
+                const uint64_t sad = __builtin_amdgcn_qsad_pk_u16_u8(src, x4, 0ull);
+                t[2 * h] = uint32_t(sad);
+                t[2 * h + 1] = uint32_t(sad >> 32);
             }
         } else {
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                const uint32_t mk = 1u << (P.s * uint32_t(k));   // s k <= alpha - s < 16
+            // byte k of the pair's q-grams sits at p0 + c and p0 + c + 1,
+            // c = PRE + 1 - Q + k + 2i
+            u16x2 acc[8];
+            if constexpr (MODE == kNolinkS8) {
+                static_assert(Q == 2, "one-to-one 16-bit windows");
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    // v_perm numbers the bytes of {src0, src1} from src1's lowest;
-                    // selector 0x0C yields a zero byte
-                    const int c = PRE + 1 - Q + k + 2 * i;
+                    // bytes c, c + 1 (low half) and c + 1, c + 2 (high half)
+                    const int c = PRE - 1 + 2 * i;
                     const int h = (c >> 2) < NWW - 2 ? (c >> 2) : NWW - 2;
                     const uint32_t o = uint32_t(c - 4 * h);
-                    const uint32_t pr = __builtin_amdgcn_perm(w[h + 1], w[h], 0x0C000C00u | o | ((o + 1u) << 16));
-                    const u16x2 r = __builtin_bit_cast(u16x2, pr);
-                    acc[i] = k == 0 ? r : acc[i] + r * u16x2{uint16_t(mk), uint16_t(mk)};
+                    acc[i] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(w[h + 1], w[h],
+                                                                             o | ((o + 1u) << 8) | ((o + 1u) << 16) |
+                                                                                 ((o + 2u) << 24)));
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    const uint32_t mk = 1u << (P.s * uint32_t(k));   // s k <= alpha - s < 16
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        // v_perm numbers the bytes of {src0, src1} from src1's
+                        // lowest; selector 0x0C yields a zero byte
+                        const int c = PRE + 1 - Q + k + 2 * i;
+                        const int h = (c >> 2) < NWW - 2 ? (c >> 2) : NWW - 2;
+                        const uint32_t o = uint32_t(c - 4 * h);
+                        const uint32_t pr = __builtin_amdgcn_perm(w[h + 1], w[h], 0x0C000C00u | o | ((o + 1u) << 16));
+                        const u16x2 r = __builtin_bit_cast(u16x2, pr);
+                        acc[i] = k == 0 ? r : acc[i] + r * u16x2{uint16_t(mk), uint16_t(mk)};
+                    }
                 }
             }
-        }
-        // per half t = (H ^ H_v) mod 2^alpha: zero exactly when the window passes
-        uint32_t t[8];
+            // t = (H ^ H_v) mod 2^alpha
 #pragma unroll
-        for (int i = 0; i < 8; ++i) t[i] = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
+            for (int i = 0; i < 8; ++i) t[i] = (__builtin_bit_cast(uint32_t, acc[i]) ^ hv2) & mask2;
+        }
         u16x2 mn = __builtin_bit_cast(u16x2, t[0]);
 #pragma unroll
         for (int i = 1; i < 8; ++i) mn = __builtin_elementwise_min(mn, __builtin_bit_cast(u16x2, t[i]));
@@ -1023,10 +1047,13 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
     if constexpr (C == 0)
     {
         if constexpr (Q == 2)
-            found = P.s == 8u ? dense_mark_nolink<2, true>(t32, tb, x32, P, S, bm)
-                              : dense_mark_nolink<2, false>(t32, tb, x32, P, S, bm);
+            found = P.s == 8u ? dense_mark_nolink<2, kNolinkS8>(t32, tb, x32, P, S, bm)
+                              : dense_mark_nolink<2, kNolinkHash>(t32, tb, x32, P, S, bm);
+        else if constexpr (Q == 3 || Q == 4)
+            found = P.m == 4u ? dense_mark_nolink<Q, kNolinkSad4>(t32, tb, x32, P, S, bm)
+                              : dense_mark_nolink<Q, kNolinkHash>(t32, tb, x32, P, S, bm);
         else
-            found = dense_mark_nolink<Q, false>(t32, tb, x32, P, S, bm);
+            found = dense_mark_nolink<Q, kNolinkHash>(t32, tb, x32, P, S, bm);
     }
     else
         found = dense_mark<Q, WT, C>(t32, tb, F, x32, P, S, bm);
