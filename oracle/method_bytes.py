@@ -65,21 +65,31 @@ def main():
     ap.add_argument("--patterns", type=int, default=4)
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--budget", type=int, default=4_000_000, help="q-grams hashed per scan at most")
+    ap.add_argument("--md-only", action="store_true",
+                    help="rewrite the markdown summary from the stored JSON table (after the tuned choices "
+                         "changed) without scanning again")
     args = ap.parse_args()
-    O.build()
-    cells = [(s, m, args.patterns, args.budget) for s in (4, 20, 64, 27) for m in LENGTHS]
-    table = {}
-    with ProcessPoolExecutor(max_workers=args.jobs) as ex:
-        for sigma, m, out in ex.map(_cell, cells):
-            table.setdefault(str(sigma), {})[str(m)] = out
-            print(f"sigma {sigma} m {m}: {min(out.values()):.3f}..{max(out.values()):.3f}", flush=True)
-    doc = {"line_bytes": LINE, "text_bytes": 256 << 20, "patterns_per_cell": args.patterns,
-           "read_fraction": table,
-           "note": "mean share of the text's 128-byte lines read by the sequential searching phase "
-                   "(oracle/hc_seq.c) for the benchmark's first patterns of each (alphabet, m); keys "
-                   "'q,alpha,w'; m <= 32 reads every line"}
-    with open(os.path.join(ROOT, "profiles", "hc_method_bytes.json"), "w") as f:
-        json.dump(doc, f, indent=1)
+    json_path = os.path.join(ROOT, "profiles", "hc_method_bytes.json")
+    if args.md_only:
+        doc = json.load(open(json_path))
+        table = doc["read_fraction"]
+        args.patterns = doc["patterns_per_cell"]
+        args.budget = doc.get("budget", args.budget)
+    else:
+        O.build()
+        cells = [(s, m, args.patterns, args.budget) for s in (4, 20, 64, 27) for m in LENGTHS]
+        table = {}
+        with ProcessPoolExecutor(max_workers=args.jobs) as ex:
+            for sigma, m, out in ex.map(_cell, cells):
+                table.setdefault(str(sigma), {})[str(m)] = out
+                print(f"sigma {sigma} m {m}: {min(out.values()):.3f}..{max(out.values()):.3f}", flush=True)
+        doc = {"line_bytes": LINE, "text_bytes": 256 << 20, "patterns_per_cell": args.patterns,
+               "budget": args.budget, "read_fraction": table,
+               "note": "mean share of the text's 128-byte lines read by the sequential searching phase "
+                       "(oracle/hc_seq.c) for the benchmark's first patterns of each (alphabet, m); keys "
+                       "'q,alpha,w'; m <= 32 reads every line"}
+        with open(json_path, "w") as f:
+            json.dump(doc, f, indent=1)
     tuned_path = os.path.join(ROOT, "profiles", "hc_search_single_pattern_tuned.json")
     tuned = json.load(open(tuned_path)) if os.path.exists(tuned_path) else {}
     lines = ["# Text bytes the HC searching phase reads (method bytes)", "",
