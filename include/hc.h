@@ -72,10 +72,10 @@ typedef struct {
  *             short shifts (m - q + 1 small), where the loop saves little,
  *             this avoids its divergence. Available for patterns without
  *             links (m < 2q, any q) and for q <= 4 with up to 3 links per
- *             window; other patterns run the segment schedule. With m = 4
- *             (no links) the window is one dword and is compared with x
- *             directly, which decides exactly what test plus verification
- *             decide. */
+ *             window; other patterns run the segment schedule. With
+ *             4 <= m <= 8 and no links the window (one or two dwords) is
+ *             compared with x directly, which decides exactly what test
+ *             plus verification decide. */
 enum { HC_SCHED_AUTO = 0, HC_SCHED_SEGMENT = 1, HC_SCHED_WAVE = 2, HC_SCHED_DENSE = 3 };
 
 /* Searching-phase variant (no effect on results).

@@ -848,13 +848,17 @@ __device__ __forceinline__ TileResult shc_tile(const uint32_t *__restrict__ t32,
 // by one permute per pair. t = (H xor H_v) mod 2^alpha per half; the 16
 // halves are folded by packed 16-bit minimums, so one test per step tells
 // whether any window passed, and only such steps take the bits one by one.
-// SAD4: m = 4 (q = 3 or 4). A window is one dword, so the filter and the
-// verification both look at the same 4 bytes: the window is compared with x
-// directly, t = the sum of absolute byte differences, zero exactly for an
-// occurrence; one quad-SAD instruction gives it for four consecutive
-// windows (the four byte offsets of an 8-byte source) as four 16-bit halves.
+// SAD4: m = 4 (q = 3 or 4). Without links the test reads the window-end
+// q-gram and verification then reads the whole window, so together they
+// decide exactly whether the window equals x; with a window of one dword the
+// kernel compares it with x directly: t = the sum of absolute byte
+// differences, zero exactly for an occurrence. One quad-SAD instruction
+// gives it for four consecutive windows (the four byte offsets of an 8-byte
+// source) as four 16-bit halves. SAD8: 5 <= m <= 8, the same with two quad
+// SADs per four windows, over the window's first and last 4 bytes (which
+// overlap when m < 8), the second accumulating onto the first.
 // The marks left are occurrences (every candidate has been compared with x).
-constexpr int kNolinkHash = 0, kNolinkS8 = 1, kNolinkSad4 = 2;
+constexpr int kNolinkHash = 0, kNolinkS8 = 1, kNolinkSad4 = 2, kNolinkSad8 = 3;
 
 template <int Q, int MODE>
 __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t32, uint32_t tb,
@@ -863,15 +867,17 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
     static_assert(Q >= 1 && Q <= 8, "q-grams of at most 8 bytes");
     typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
     // the words loaded start PRE bytes before the first window end
-    constexpr int PRE = Q <= 4 ? 3 : 7;
+    constexpr int PRE = (Q <= 4 && MODE != kNolinkSad8) ? 3 : 7;
     constexpr int NWW = (PRE + 15) / 4 + 1;   // aligned words covering the 16 q-grams
     uint16_t *bm16 = reinterpret_cast<uint16_t *>(bm);
     const uint32_t steps = (S + 15u) / 16u;
     const uint32_t mask2 = P.mask | (P.mask << 16), hv2 = P.hv | (P.hv << 16);
     // q = m and s >= 8: the hash is one-to-one on windows (each byte in its
     // own 8 bits), so a window passes the test exactly when it equals x
-    const bool exact = MODE == kNolinkSad4 || (P.m == uint32_t(Q) && P.s >= 8u);
-    const uint32_t x4 = x32[0];   // SAD4: the pattern's 4 bytes
+    const bool exact = MODE == kNolinkSad4 || MODE == kNolinkSad8 || (P.m == uint32_t(Q) && P.s >= 8u);
+    // SAD4 / SAD8: the pattern's first 4 bytes, and its last 4 (SAD8)
+    const uint32_t x4 = x32[0];
+    const uint32_t x4last = uint32_t(((uint64_t(x32[1]) << 32) | x32[0]) >> (8u * ((P.m - 4u) & 7u)));
     uint32_t cmask = 0;   // this lane's steps with candidates
     uint32_t ks = 0;
     for (uint32_t g = threadIdx.x; g < steps; g += kThreads, ++ks) {
@@ -895,6 +901,23 @@ __device__ __forceinline__ bool dense_mark_nolink(const uint32_t *__restrict__ t
             for (int h = 0; h < 4; ++h) {
                 const uint64_t src = (uint64_t(w[h + 1]) << 32) | w[h];
                 const uint64_t sad = __builtin_amdgcn_qsad_pk_u16_u8(src, x4, 0ull);
+                t[2 * h] = uint32_t(sad);
+                t[2 * h + 1] = uint32_t(sad >> 32);
+            }
+        } else if constexpr (MODE == kNolinkSad8) {
+            // p0 = the first window's start - (8 - m): window 4h + k has its
+            // last 4 bytes at byte 4 + 4h + k of the words and its first 4 at
+            // byte (8 - m) + 4h + k, i.e. byte 4h + k of the words f
+            const uint32_t o = 8u - P.m;   // 0..3
+            uint32_t f[NWW - 1];
+#pragma unroll
+            for (int i = 0; i < NWW - 1; ++i) f[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], o);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const uint64_t first = (uint64_t(f[h + 1]) << 32) | f[h];
+                const uint64_t last = (uint64_t(w[h + 2]) << 32) | w[h + 1];
+                const uint64_t sad = __builtin_amdgcn_qsad_pk_u16_u8(
+                    last, x4last, __builtin_amdgcn_qsad_pk_u16_u8(first, x4, 0ull));
                 t[2 * h] = uint32_t(sad);
                 t[2 * h + 1] = uint32_t(sad >> 32);
             }
@@ -1046,11 +1069,16 @@ __device__ __forceinline__ TileResult dense_tile(const uint32_t *__restrict__ t3
     bool found;
     if constexpr (C == 0)
     {
+        // windows of 4 to 8 bytes are compared with x directly (SAD4, SAD8)
         if constexpr (Q == 2)
             found = P.s == 8u ? dense_mark_nolink<2, kNolinkS8>(t32, tb, x32, P, S, bm)
                               : dense_mark_nolink<2, kNolinkHash>(t32, tb, x32, P, S, bm);
         else if constexpr (Q == 3 || Q == 4)
-            found = P.m == 4u ? dense_mark_nolink<Q, kNolinkSad4>(t32, tb, x32, P, S, bm)
+            found = P.m == 4u  ? dense_mark_nolink<Q, kNolinkSad4>(t32, tb, x32, P, S, bm)
+                    : P.m >= 5u ? dense_mark_nolink<Q, kNolinkSad8>(t32, tb, x32, P, S, bm)   // m < 2q <= 8
+                                : dense_mark_nolink<Q, kNolinkHash>(t32, tb, x32, P, S, bm);
+        else if constexpr (Q >= 5)   // m >= q >= 5
+            found = P.m <= 8u ? dense_mark_nolink<Q, kNolinkSad8>(t32, tb, x32, P, S, bm)
                               : dense_mark_nolink<Q, kNolinkHash>(t32, tb, x32, P, S, bm);
         else
             found = dense_mark_nolink<Q, kNolinkHash>(t32, tb, x32, P, S, bm);

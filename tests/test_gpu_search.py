@@ -342,6 +342,37 @@ def test_dense_without_links(torch_dev):
                     assert c == want.size and np.array_equal(got, want), (sigma, m, q, alpha, w)
 
 
+def test_dense_direct_comparison_edges(torch_dev):
+    """Windows of 4-8 bytes without links are compared with x directly (sums
+    of absolute byte differences over the first and last 4 bytes): copies of
+    x planted at both text ends and across tile boundaries, next to near
+    misses that differ in one byte only (first, middle or last), patterns
+    holding the byte values 0x00 and 0xFF."""
+    g = np.random.default_rng(29)
+    seg = 64
+    tile = 256 * seg
+    n = 3 * tile + 17
+    for m in range(4, 9):
+        for q in range((m + 2) // 2, min(m, 8) + 1):
+            y = g.integers(0, 256, size=n, dtype=np.uint8)
+            x = g.integers(0, 256, size=m, dtype=np.uint8)
+            x[0], x[-1] = 0x00, 0xFF
+            spots = [0, n - m, tile - 1, tile - m + 1, 2 * tile - 3, int(g.integers(0, n - m))]
+            for t in spots:
+                y[t:t + m] = x
+            for k, t in enumerate((tile + 100, tile + 200, tile + 300)):
+                miss = x.copy()
+                j = (0, m // 2, m - 1)[k]
+                miss[j] ^= 0x01
+                y[t:t + m] = miss
+            xb = x.tobytes()
+            want = O.occurrences(xb, y)
+            for alpha, w in ((8, 8), (12, 16)):
+                announce("dense direct comparison", m, q, alpha, w)
+                got, c = gpu_occ(xb, to_dev(y, torch_dev), (q, alpha, w), (seg, B.HC_SCHED_DENSE, 0, 0))
+                assert c == want.size and np.array_equal(got, want), (m, q, alpha, w)
+
+
 def test_markov_full_size_sampled(torch_dev):
     """The 256 MiB order-2 Markov text (the skewed-text workload), library
     defaults, two sampled patterns per length, complete lists compared."""
