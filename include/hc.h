@@ -101,7 +101,7 @@ enum { HC_VARIANT_AUTO = 0, HC_VARIANT_HC = 1, HC_VARIANT_SENTINEL = 2, HC_VARIA
 /* Launch shape of the search kernel. A field set to 0 is chosen by the
  * library (the autotuner's cache, else built-in priors: the dense schedule
  * on tiles of 16384 starts for patterns without links, m < 2q, which the
- * default q gives every m <= 7 and m = 8 over at most 4 distinct bytes;
+ * default q gives every m <= 8;
  * else the segment schedule on tiles of 25600 starts). */
 typedef struct {
     int32_t segment;     /* window starts per lane; tile = 256 * segment     */

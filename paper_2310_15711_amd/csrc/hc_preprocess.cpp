@@ -60,9 +60,10 @@ Tuned get_tuned(int64_t m) {
 // pattern length and the number of distinct bytes of x (a stand-in for the
 // alphabet of the text). Section 4 reports best variants with q between 3 and
 // 8 and alpha 11-12; on gfx950 the fastest choices measured on iid texts over
-// 4 to 64 symbols were: for m <= 7 the smallest q with m < 2q (no links: the
-// test of every window is one hash, which the dense schedule evaluates for
-// all windows at once), longer q-grams for small alphabets above that,
+// 4 to 64 symbols were: for m <= 8 the smallest q with m < 2q (no links:
+// the dense schedule tests every window at once, by one hash, or for
+// windows of 4 to 8 bytes by comparing them with x directly), longer q-grams
+// for small alphabets above that,
 // smaller tables (alpha 11, 16-bit words: more workgroups fit in LDS) for m
 // up to 128. An entry measured by hc_autotune for the pattern's length bucket
 // takes precedence.
@@ -70,8 +71,7 @@ void default_params(int64_t m, int distinct, int &q, int &alpha, int &w) {
     const bool small_sigma = distinct <= 4;
     int pq, pa, pw;
     if (m <= 2) { pq = int(m); pa = 8; pw = 8; }
-    else if (m <= 7) { pq = int(std::min<int64_t>(4, (m + 2) / 2)); pa = 10; pw = 16; }
-    else if (m <= 8) { pq = small_sigma ? 5 : 3; pa = 12; pw = 32; }
+    else if (m <= 8) { pq = int((m + 2) / 2); pa = 10; pw = 16; }
     else if (m <= 16) { pq = small_sigma ? 5 : 4; pa = 12; pw = 32; }
     else if (m <= 128) { pq = 5; pa = 11; pw = 16; }
     else if (m <= 256) { pq = 5; pa = 12; pw = 32; }

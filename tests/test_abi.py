@@ -144,11 +144,12 @@ def test_bucket_defaults_after_reset():
 
 
 def test_short_patterns_default_to_no_links():
-    """Untuned, every m <= 7 gets the smallest q with m < 2q (no links: the
-    dense schedule's single-hash test), with s = floor(alpha / q) >= 1."""
+    """Untuned, every m <= 8 gets the smallest q with m < 2q (no links: the
+    dense schedule's single-hash test, or its direct comparison of windows
+    of 4 to 8 bytes), with s = floor(alpha / q) >= 1."""
     B.hc_autotune_reset()
-    for m in range(1, 8):
-        for x in (b"ACGTACG"[:m], bytes(range(40, 40 + m))):
+    for m in range(1, 9):
+        for x in (b"ACGTACGT"[:m], bytes(range(40, 40 + m))):
             info = B.hc_pattern_info(B.hc_preprocess(x))
             q = info["q"]
             assert m < 2 * q and (q == 1 or m >= 2 * (q - 1)), (m, q)
